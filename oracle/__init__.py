@@ -1,0 +1,31 @@
+"""Float64 CPU oracle of the GPAIR hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  It shares no code with
+the HIP path (``paper_2602_03893_amd``) and neither imports the other; the only
+common module is the seeded input generator ``paper_2602_03893_amd.inputs``,
+which holds none of the method's arithmetic and is imported by the tests, not by
+this package.
+
+Contents
+ - ``ops``      forward / adjoint / sigma-gradient of the direct operator (C,
+                float64, OpenMP), Eq. (single_forward) with the n_sigma window.
+ - ``physics``  closed forms of the Methods derivation (sphere integral,
+                two-term pressure) and their numerical Poisson-integral checks.
+ - ``solvers``  relative residual, power iteration, projected gradient and Adam
+                loops in float64 on top of ``ops``.
+
+Pins (what each function is checked against, in ``tests/``):
+ - ``ops.forward``   numerical Poisson integral, Eq. (pa_wave), by quadrature
+                     (independent of the closed form); special values; linearity;
+                     translation / rotation invariance; window edges.
+ - ``ops.adjoint``   the dot-product test <A x, y> = <x, A^T y> against the pinned
+                     forward; gA and gsigma against central finite differences of
+                     the pinned forward.
+ - ``physics``       Gauss-Legendre quadrature of the surface integral and a
+                     numerical derivative of Eq. (pa_wave).
+ - ``solvers.pgd``   converges to scipy's NNLS solution (a different algorithm).
+ - ``solvers.adam``  matches torch.optim.Adam (a library implementation) step by
+                     step on the same gradients.
+"""
+from . import ops, physics, solvers  # noqa: F401

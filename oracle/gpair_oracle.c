@@ -1,0 +1,152 @@
+/*
+ * gpair_oracle.c -- plain float64 CPU oracle of the GPAIR direct operators.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only tests/, the smoke check and the CPU-baseline
+ * leg of the benchmark may load this library.  It shares no code with the HIP
+ * path and must never be used as a fallback for it.
+ *
+ * What it computes (arXiv 2602.03893, Methods):
+ *  - the pressure a single isotropic Gaussian kernel (amplitude A, width
+ *    sigma, centre at distance r from the detector) produces at time t,
+ *    keeping only the outgoing term: Eq. (single_forward),
+ *        p = A/(2r) * d * exp(-d^2/(2 sigma^2)),  d = r - v t;
+ *  - kept only inside the window |d| <= n_sigma*sigma (the "3 sigma
+ *    principle" that follows that equation; inclusive edges);
+ *  - summed over all kernels (linearity of the wave equation, stated at the
+ *    start of the Methods section) and evaluated at every sample t = t0 + n dt
+ *    of every sensor: the direct enumeration over source-detector pairs the
+ *    paper describes at the start of the "Adaptive supersampling alignment"
+ *    subsection;
+ *  - the transpose of that linear map (the "Adjoint Operator" subsection's
+ *    principle: the adjoint is the transpose of the forward), and the
+ *    derivative of Eq. (single_forward) with respect to sigma.
+ *
+ * Everything is float64 with plain loops; inputs are the float32 arrays the
+ * GPU receives, promoted exactly.  Window membership of each candidate sample
+ * is decided by evaluating |d| <= n_sigma*sigma directly.  Build with
+ * -ffp-contract=off so every operation is separately rounded.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+
+/* r = |s - c| in float64 from float32 coordinates. */
+static double pair_distance(const float *s, float cx, float cy, float cz) {
+  double dx = (double)s[0] - (double)cx;
+  double dy = (double)s[1] - (double)cy;
+  double dz = (double)s[2] - (double)cz;
+  return sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+/* Candidate sample range [lo, hi] (clipped to the trace) that surely contains
+ * every n with |r - v (t0 + n dt)| <= half; membership is then tested per n. */
+static void candidate_range(double r, double half, double v, double dt,
+                            double t0, int64_t nt, int64_t *lo, int64_t *hi) {
+  double a = (r - half) / v - t0;
+  double b = (r + half) / v - t0;
+  int64_t l = (int64_t)floor(a / dt) - 1;
+  int64_t h = (int64_t)ceil(b / dt) + 1;
+  if (l < 0) l = 0;
+  if (h > nt - 1) h = nt - 1;
+  *lo = l;
+  *hi = h;
+}
+
+/*
+ * Forward: y[j*nt + n] = sum_k [|d| <= nsig*sigma_k] A_k/(2r) d exp(-d^2/(2 sigma_k^2)).
+ * y is float64 [nd][nt], overwritten.
+ */
+void oracle_forward(int64_t m, const float *cx, const float *cy,
+                    const float *cz, const double *amp, const double *sigma,
+                    int64_t nd, const float *sensors, int64_t nt, double dt,
+                    double t0, double v, double nsig, double *y) {
+  int64_t j;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (j = 0; j < nd; ++j) {
+    double *row = y + j * nt;
+    for (int64_t n = 0; n < nt; ++n) row[n] = 0.0;
+    const float *s = sensors + 3 * j;
+    for (int64_t k = 0; k < m; ++k) {
+      double r = pair_distance(s, cx[k], cy[k], cz[k]);
+      double sg = (double)sigma[k];
+      double half = nsig * sg;
+      double a = (double)amp[k];
+      int64_t lo, hi;
+      candidate_range(r, half, v, dt, t0, nt, &lo, &hi);
+      for (int64_t n = lo; n <= hi; ++n) {
+        double t = t0 + (double)n * dt;
+        double d = r - v * t;
+        if (fabs(d) <= half) {
+          row[n] += a / (2.0 * r) * d * exp(-(d * d) / (2.0 * sg * sg));
+        }
+      }
+    }
+  }
+}
+
+/*
+ * Adjoint: gA[k] = sum_j sum_{n in W} delta[j][n] d e / (2r);
+ *          gsig[k] = sum_j sum_{n in W} delta[j][n] A_k d^3 e / (2 r sigma_k^3).
+ * delta is float64 [nd][nt]; gA, gsig float64 [m], overwritten (gsig may be
+ * NULL).
+ */
+void oracle_adjoint(int64_t m, const float *cx, const float *cy,
+                    const float *cz, const double *amp, const double *sigma,
+                    int64_t nd, const float *sensors, int64_t nt, double dt,
+                    double t0, double v, double nsig, const double *delta,
+                    double *ga, double *gsig) {
+  int64_t k;
+#pragma omp parallel for schedule(static)
+  for (k = 0; k < m; ++k) {
+    double sg = (double)sigma[k];
+    double half = nsig * sg;
+    double acc_a = 0.0, acc_s = 0.0;
+    for (int64_t j = 0; j < nd; ++j) {
+      const float *s = sensors + 3 * j;
+      double r = pair_distance(s, cx[k], cy[k], cz[k]);
+      int64_t lo, hi;
+      candidate_range(r, half, v, dt, t0, nt, &lo, &hi);
+      for (int64_t n = lo; n <= hi; ++n) {
+        double t = t0 + (double)n * dt;
+        double d = r - v * t;
+        if (fabs(d) <= half) {
+          double e = exp(-(d * d) / (2.0 * sg * sg));
+          double dl = delta[j * nt + n];
+          acc_a += dl * d * e / (2.0 * r);
+          acc_s += dl * d * d * d * e / (2.0 * r);
+        }
+      }
+    }
+    ga[k] = acc_a;
+    if (gsig) gsig[k] = acc_s * (double)amp[k] / (sg * sg * sg);
+  }
+}
+
+/*
+ * Number of in-window taps of every pair, summed (the work count the
+ * benchmark reports), and the number of pairs with at least one tap.
+ */
+void oracle_count_taps(int64_t m, const float *cx, const float *cy,
+                       const float *cz, const double *sigma, int64_t nd,
+                       const float *sensors, int64_t nt, double dt, double t0,
+                       double v, double nsig, int64_t *taps, int64_t *pairs) {
+  int64_t total = 0, live = 0, j;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : total, live)
+  for (j = 0; j < nd; ++j) {
+    const float *s = sensors + 3 * j;
+    for (int64_t k = 0; k < m; ++k) {
+      double r = pair_distance(s, cx[k], cy[k], cz[k]);
+      double half = nsig * (double)sigma[k];
+      int64_t lo, hi, c = 0;
+      candidate_range(r, half, v, dt, t0, nt, &lo, &hi);
+      for (int64_t n = lo; n <= hi; ++n) {
+        double d = r - v * (t0 + (double)n * dt);
+        if (fabs(d) <= half) ++c;
+      }
+      total += c;
+      if (c) ++live;
+    }
+  }
+  *taps = total;
+  *pairs = live;
+}
