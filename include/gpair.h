@@ -1,0 +1,378 @@
+/*
+ * gpair.h -- C ABI of the GPAIR direct-evaluation operators on MI355X (gfx950).
+ *
+ * GPAIR (Gaussian-kernel-based ultrafast 3D photoacoustic iterative
+ * reconstruction, arXiv 2602.03893) represents the initial pressure as a sum of
+ * isotropic Gaussian kernels (Methods, "Gaussian-kernel-based distribution for
+ * the continuous source discretization", first two equations) and models the
+ * pressure each kernel produces at a point detector in closed form, Eq.
+ * (single_forward): p = A/(2r) * d * exp(-d^2/(2 sigma^2)), d = r - v t, kept
+ * only inside the window |d| <= n_sigma * sigma (the "3 sigma principle" stated
+ * right after that equation).  This library evaluates that sum directly for
+ * every kernel, sensor and in-window sample (the "straightforward approach" the
+ * paper describes at the start of the "Adaptive supersampling alignment"
+ * subsection), with a per-kernel width sigma_k, and its exact transpose.
+ *
+ * Conventions shared by every entry point
+ *  - Units are SI: metres, seconds, metres per second.
+ *  - "device" pointers are HIP device memory owned by the caller (for instance
+ *    torch tensors); "host" pointers are ordinary host memory owned by the
+ *    caller.  The library never allocates or frees device memory: the caller
+ *    supplies every device buffer, workspaces included.
+ *  - Traces are float32, row-major [n_sensors][n_samples] (time contiguous).
+ *    Sample n of every sensor is taken at time t0 + n*dt.
+ *  - Kernel arrays (A, sigma, gA, gsigma) are float32 [n_kernels] in the
+ *    caller's kernel order (the order of cx/cy/cz at plan creation).
+ *  - Work is enqueued on the given HIP stream (NULL = the legacy default
+ *    stream).  Calls return once the work is enqueued; device faults surface at
+ *    the caller's next synchronisation.  Arguments are validated on the host
+ *    before anything is launched: on a negative status nothing was launched and
+ *    no output was touched.  No C++ exception crosses this boundary.
+ *  - A plan is immutable after creation, but its workspace holds per-call
+ *    scratch (per-kernel coefficient records): calls that use one plan must be
+ *    ordered on one stream; concurrent calls on one plan race.
+ *  - Outputs are overwritten, never accumulated into.
+ */
+#ifndef GPAIR_H
+#define GPAIR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GPAIR_ABI_VERSION 1
+
+/* Identical to hipStream_t. */
+typedef struct ihipStream_t *gpair_stream;
+
+typedef enum gpair_status {
+  GPAIR_OK = 0,
+  GPAIR_NOT_CONVERGED = 1,     /* solver: iteration cap reached before tol  */
+  GPAIR_ERR_INVALID_ARG = -1,  /* null pointer, bad size, bad scalar        */
+  GPAIR_ERR_NEAR_FIELD = -2,   /* a kernel lies closer than 10*sigma_max to
+                                  a sensor: the dropped incoming-wave term
+                                  of the two-term pressure is not negligible */
+  GPAIR_ERR_NONFINITE = -3,    /* NaN/Inf met (geometry, or solver state)   */
+  GPAIR_ERR_HIP = -4,          /* a HIP runtime call or launch failed        */
+  GPAIR_ERR_WORKSPACE = -5,    /* workspace null, too small or misaligned    */
+  GPAIR_ERR_SIGMA_RANGE = -6   /* a sigma_k outside (0, sigma_max] was seen  */
+} gpair_status;
+
+/* Human-readable name of a status; never NULL. */
+const char *gpair_status_string(gpair_status st);
+
+/* GPAIR_ABI_VERSION of the built library. */
+int gpair_abi_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* a0. Plan: geometry, spatial tiling, workspace                              */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Acquisition geometry and operator constants.
+ *  cx, cy, cz   host float32 [n_kernels]: kernel centres c_k (the voxel
+ *               centres r_i of the source model).  Any point cloud is allowed;
+ *               a regular grid tiles best.
+ *  sensors      host float32 [n_sensors][3]: point-detector positions s_j.
+ *  n_samples    samples per trace N_t; sample n is at t0 + n*dt.
+ *  dt, t0       sampling interval (> 0) and time of sample 0.  Kept in double
+ *               because r - v t must be resolved to ~1e-11 m at r ~ 4e-2 m.
+ *  c_sound      speed of sound v (> 0).
+ *  n_sigma      window half-width in units of sigma (> 0; 3 in the paper).
+ *  sigma_max    upper bound of every sigma_k passed later (> 0).  It sizes
+ *               the per-tile time segments; a larger sigma_k is an error.
+ *  fwd_tile     most kernels per forward workgroup, 0 = automatic, else a
+ *               power of two in [64, 8192].
+ *  adj_tile     most kernels per adjoint workgroup, 0 = automatic (256),
+ *               else 64, 128 or 256.
+ *  fwd_waves    sensor groups of 64 per forward workgroup, 0 = automatic,
+ *               else 1, 2 or 4 (reduced if the LDS segments do not fit).
+ */
+typedef struct gpair_geometry {
+  int64_t n_kernels;
+  const float *cx;
+  const float *cy;
+  const float *cz;
+  int32_t n_sensors;
+  const float *sensors;
+  int32_t n_samples;
+  double dt;
+  double t0;
+  double c_sound;
+  double n_sigma;
+  double sigma_max;
+  int32_t fwd_tile;
+  int32_t adj_tile;
+  int32_t fwd_waves;
+} gpair_geometry;
+
+typedef struct gpair_plan_s *gpair_plan;
+
+/* Read-only description of a plan (for tests, tuning and reports). */
+typedef struct gpair_plan_info {
+  int64_t n_kernels;
+  int32_t n_sensors;
+  int32_t n_samples;
+  int32_t fwd_tile;          /* kernels per forward workgroup              */
+  int32_t adj_tile;          /* kernels per adjoint workgroup              */
+  int32_t fwd_waves;         /* sensor groups per forward workgroup        */
+  int64_t fwd_tiles;         /* number of forward tiles                    */
+  int64_t adj_tiles;         /* number of adjoint tiles                    */
+  int32_t fwd_segment;       /* samples in a forward LDS trace segment     */
+  int32_t adj_segment;       /* samples in an adjoint LDS residual segment */
+  int32_t max_taps;          /* taps per pair at sigma_max                 */
+  double max_tile_radius;    /* largest tile bounding radius (m)           */
+  double min_distance;       /* lower bound of the kernel-sensor distances */
+  size_t workspace_bytes;
+} gpair_plan_info;
+
+/*
+ * Validate g and tile the kernels into compact spatial tiles (aligned blocks
+ * of the kernel lattice in Morton order; quantised positions for a point
+ * cloud).  Host-only: g and its host arrays are read during the call and not
+ * retained.  The plan must then be bound to a device workspace
+ * (gpair_plan_bind_workspace) before any operator call.
+ * Errors: INVALID_ARG, NONFINITE (geometry), NEAR_FIELD.  On error *out is
+ * set to NULL.
+ */
+gpair_status gpair_plan_create(const gpair_geometry *g, gpair_plan *out);
+
+/* Bytes of device workspace the plan needs.  Errors: INVALID_ARG. */
+gpair_status gpair_plan_workspace_size(gpair_plan p, size_t *bytes);
+
+/*
+ * Upload the plan's tables (float64 sensors and centres, tile bounding
+ * spheres, kernel permutation) into the caller's device workspace
+ * (>= gpair_plan_workspace_size bytes, 256-byte aligned).  The workspace must
+ * outlive every later call on the plan and must not be shared with another
+ * plan.  Synchronous with respect to `stream`.  May be called again to move
+ * the plan to another workspace.  Errors: INVALID_ARG, WORKSPACE, HIP.
+ */
+gpair_status gpair_plan_bind_workspace(gpair_plan p, void *workspace,
+                                       size_t workspace_bytes,
+                                       gpair_stream stream);
+
+/* Release the host-side plan object (the workspace stays the caller's). */
+void gpair_plan_destroy(gpair_plan p);
+
+/* Fill *info.  Errors: INVALID_ARG. */
+gpair_status gpair_plan_get_info(gpair_plan p, gpair_plan_info *info);
+
+/* ------------------------------------------------------------------------ */
+/* a1 + a2. Forward operator                                                  */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * y = A(x): for every sensor j and sample n,
+ *   y_j[n] = sum_k [ |d| <= n_sigma*sigma_k ] * A_k/(2 r_jk) * d
+ *            * exp(-d^2 / (2 sigma_k^2)),   d = r_jk - v (t0 + n dt),
+ * i.e. Eq. (single_forward) summed over the kernels by linearity of the wave
+ * equation, with the window of the "3 sigma principle" (inclusive) and
+ * samples outside [0, n_samples) dropped.  r_jk = |s_j - c_k| and the window
+ * membership are decided in float64; taps are evaluated in float32.
+ *  A      device float32 [n_kernels]  amplitudes A_k (any sign).
+ *  sigma  device float32 [n_kernels]  widths sigma_k in (0, sigma_max].
+ *  y      device float32 [n_sensors][n_samples], overwritten.
+ * A sigma_k outside (0, sigma_max] is clamped into range for that kernel and
+ * counted (see gpair_sigma_violations); the call still returns GPAIR_OK.
+ * Errors: INVALID_ARG, HIP.
+ */
+gpair_status gpair_forward(gpair_plan p, const float *A, const float *sigma,
+                           float *y, gpair_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* a3. Adjoint operator (gradient with respect to A and sigma)                */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * The exact transpose of gpair_forward (the transposition principle of the
+ * "Adjoint Operator" subsection, applied to the direct sum) and the
+ * sigma-derivative of Eq. (single_forward):
+ *   gA_k     = sum_j sum_{n in W_jk} delta_j[n] * d * e / (2 r_jk)
+ *   gsigma_k = sum_j sum_{n in W_jk} delta_j[n] * A_k * d^3 * e
+ *                                    / (2 r_jk sigma_k^3)
+ * with e = exp(-d^2/(2 sigma_k^2)) and W_jk the same window as the forward.
+ * For a loss L(y) with dL/dy = delta these are dL/dA_k and dL/dsigma_k (the
+ * window indicator is locally constant in sigma, so it has no derivative).
+ *  A       device float32 [n_kernels]; read only when gsigma != NULL (may
+ *          then be NULL otherwise).
+ *  sigma   device float32 [n_kernels].
+ *  delta   device float32 [n_sensors][n_samples].
+ *  gA      device float32 [n_kernels], overwritten.
+ *  gsigma  device float32 [n_kernels], overwritten, or NULL to skip.
+ * Sums over sensors are carried in float64.  Errors: INVALID_ARG, HIP.
+ */
+gpair_status gpair_adjoint(gpair_plan p, const float *A, const float *sigma,
+                           const float *delta, float *gA, float *gsigma,
+                           gpair_stream stream);
+
+/*
+ * Synchronise `stream` and return in *count how many sigma_k values outside
+ * (0, sigma_max] the operators have met since the plan was created (each
+ * forward/adjoint call adds its count).  Errors: INVALID_ARG, HIP.
+ */
+gpair_status gpair_sigma_violations(gpair_plan p, int64_t *count,
+                                    gpair_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* a4. Residual and norms                                                     */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * delta = scale * (y - b) over the plan's n_sensors*n_samples samples, and
+ * norms[0] = sum (y - b)^2, norms[1] = sum b^2, both float64 summed in a fixed
+ * order (bitwise reproducible).  The residual of Algorithm 2 ("Loss
+ * Calculation" and the trace gradient y - b) with the caller's scale.
+ *  y, b    device float32 [n_sensors][n_samples].
+ *  delta   device float32, same shape, overwritten; may alias y; may be NULL
+ *          (norms only).
+ *  norms   device float64 [2], overwritten.
+ * Uses the plan workspace for partial sums.  Errors: INVALID_ARG, HIP.
+ */
+gpair_status gpair_residual(gpair_plan p, const float *y, const float *b,
+                            float scale, float *delta, double *norms,
+                            gpair_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* a5. Parameter updates                                                      */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Projected gradient step x <- min(hi, max(lo, x - step * g)) over n
+ * elements ("hard clipping" projection named in the "Nonnegative
+ * parameterization constraint" subsection, with lo = 0, hi = +inf for A >= 0).
+ *  x  device float32 [n], updated in place;  g  device float32 [n].
+ * Errors: INVALID_ARG, HIP.
+ */
+gpair_status gpair_pgd_update(int64_t n, float *x, const float *g, float step,
+                              float lo, float hi, gpair_stream stream);
+
+/*
+ * One Adam step (the optimiser of the "Optimization formulation and
+ * algorithm" subsection; Kingma and Ba's update with bias correction) on n
+ * elements, followed by the projection x <- min(hi, max(lo, x)):
+ *   g' = grad_scale * g;  m = b1 m + (1-b1) g';  v = b2 v + (1-b2) g'^2;
+ *   x -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+ *  x, m, v  device float32 [n], updated in place (m, v start at zero);
+ *  g        device float32 [n];  t  1-based step count.
+ * Errors: INVALID_ARG, HIP.
+ */
+gpair_status gpair_adam_update(int64_t n, float *x, const float *g, float *m,
+                               float *v, float grad_scale, float lr,
+                               float beta1, float beta2, float eps, int32_t t,
+                               float lo, float hi, gpair_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* a6. Iterative reconstruction driver                                        */
+/* ------------------------------------------------------------------------ */
+
+#define GPAIR_SOLVE_PGD 0
+#define GPAIR_SOLVE_ADAM 1
+
+/*
+ * Options of gpair_solve.  The loss is 0.5*||A(x) - b||^2 / ||b||^2 (the data
+ * term of the paper's objective up to a constant factor, so that Adam sees
+ * scale-free gradients); PGD uses 0.5*||A(x) - b||^2 with step `step`.
+ *  method        GPAIR_SOLVE_PGD or GPAIR_SOLVE_ADAM.
+ *  max_iters     iteration cap (>= 0).
+ *  tol           stop when ||A(x) - b|| / ||b|| <= tol (0 disables).
+ *  step          PGD step size (e.g. 1 / ||A^T A||).
+ *  lr_A, lr_sigma, beta1, beta2, eps   Adam hyper-parameters.
+ *  learn_sigma   non-zero: also update sigma (Adam only).
+ *  sigma_lo, sigma_hi   clamp of sigma after each update (sigma_hi <=
+ *                the plan's sigma_max).
+ *  a_lo, a_hi    clamp of A after each update (a_lo = 0 gives A >= 0).
+ *  check_every   read the residual back to the host every this many
+ *                iterations (>= 1); the stop test runs only then.
+ */
+typedef struct gpair_solve_opts {
+  int32_t method;
+  int32_t max_iters;
+  double tol;
+  double step;
+  double lr_A;
+  double lr_sigma;
+  double beta1;
+  double beta2;
+  double eps;
+  int32_t learn_sigma;
+  double sigma_lo;
+  double sigma_hi;
+  double a_lo;
+  double a_hi;
+  int32_t check_every;
+} gpair_solve_opts;
+
+/*
+ * Report of gpair_solve (host memory).
+ *  history   host float64 [max_iters + 1] or NULL: relative residual before
+ *            each iteration (entry i = rho(x_i)) and after the last one, for
+ *            the iterations at which it was read (others are set to -1).
+ */
+typedef struct gpair_solve_report {
+  int32_t iters;
+  double rel_residual;
+  double seconds;
+  int32_t converged;
+  double *history;
+} gpair_solve_report;
+
+/* Device workspace bytes gpair_solve needs for (p, o). */
+gpair_status gpair_solve_workspace_size(gpair_plan p,
+                                        const gpair_solve_opts *o,
+                                        size_t *bytes);
+
+/*
+ * Algorithm 2 without its regulariser, non-negativity parameterisation and
+ * learning-rate schedule (the data-fidelity loop): from the caller's start,
+ * repeat forward -> residual -> adjoint -> update until rho <= tol or
+ * max_iters.  One host synchronisation every check_every iterations.
+ *  b       device float32 [n_sensors][n_samples]  measured traces.
+ *  A       device float32 [n_kernels]  in: start, out: result.
+ *  sigma   device float32 [n_kernels]  in/out (updated iff learn_sigma).
+ *  workspace  device, >= gpair_solve_workspace_size bytes, 256-B aligned.
+ *  r       host report (filled on GPAIR_OK and GPAIR_NOT_CONVERGED).
+ * Returns GPAIR_OK when converged, GPAIR_NOT_CONVERGED at the cap,
+ * GPAIR_ERR_NONFINITE if the residual became NaN/Inf (A, sigma then hold the
+ * last finite-checked state's successor), or another error.
+ */
+gpair_status gpair_solve(gpair_plan p, const float *b, float *A, float *sigma,
+                         const gpair_solve_opts *o, void *workspace,
+                         size_t workspace_bytes, gpair_solve_report *r,
+                         gpair_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* Kernel timing (measurement support)                                        */
+/* ------------------------------------------------------------------------ */
+
+#define GPAIR_TIMER_FORWARD 0 /* main forward kernel of the last forward  */
+#define GPAIR_TIMER_ADJOINT 1 /* main adjoint kernel of the last adjoint  */
+
+#define GPAIR_TIMER_SLOTS 64   /* launches remembered per kind              */
+
+/*
+ * enable != 0: record a pair of HIP events around the main kernel of each
+ * later forward/adjoint call, on the call's stream (the events are created
+ * here, once per plan).  Errors: INVALID_ARG, HIP.
+ */
+gpair_status gpair_plan_set_timing(gpair_plan p, int enable);
+
+/*
+ * Durations (ms) of the main kernel of the most recent calls of kind `which`
+ * recorded since timing was enabled or since the previous read (at most
+ * GPAIR_TIMER_SLOTS, oldest first).  Synchronises on the last recorded event.
+ * Writes min(count, capacity) values to ms (host float32 [capacity]) and the
+ * number available to *count, then forgets them.
+ * Errors: INVALID_ARG (timing off), HIP.
+ */
+gpair_status gpair_plan_kernel_times(gpair_plan p, int which, float *ms,
+                                     int32_t capacity, int32_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPAIR_H */

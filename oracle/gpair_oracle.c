@@ -150,3 +150,13 @@ void oracle_count_taps(int64_t m, const float *cx, const float *cy,
   *taps = total;
   *pairs = live;
 }
+
+/* Threads the OpenMP loops above use (reported with CPU timings). */
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+  extern int omp_get_max_threads(void);
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

@@ -48,8 +48,15 @@ def _load():
     lib.oracle_count_taps.argtypes = [_i64, _f32p, _f32p, _f32p, _f64p, _i64,
                                       _f32p, _i64, _dbl, _dbl, _dbl, _dbl,
                                       ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
+    lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_num_threads.argtypes = []
     _lib = lib
     return lib
+
+
+def num_threads():
+    """OpenMP threads the oracle loops use."""
+    return int(_load().oracle_num_threads())
 
 
 class Geometry:

@@ -1,0 +1,226 @@
+"""Python front end of libgpair: plans, operators, residual, updates, solver.
+
+Thin marshalling over the C ABI (include/gpair.h): torch supplies device
+memory and the current HIP stream, and every step runs in the library's HIP
+kernels.  Shapes and dtypes are checked here because the C ABI receives bare
+pointers.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import GpairError, check
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, name, numel=None, dtype=torch.float32, device=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name}: expected {numel} elements, got {t.numel()}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name}: on {t.device}, plan is on {device}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A bound plan: geometry + spatial tiling + device workspace.
+
+    centres  (M, 3) kernel centres in metres (host array-like, taken as float32)
+    sensors  (N_d, 3) sensor positions in metres
+    n_samples, dt, t0, c_sound, n_sigma, sigma_max: see gpair_geometry.
+    """
+
+    def __init__(self, centres, sensors, n_samples, dt, c_sound, n_sigma=3.0,
+                 sigma_max=None, t0=0.0, fwd_tile=0, adj_tile=0, fwd_waves=0,
+                 device=None):
+        if sigma_max is None:
+            raise ValueError("sigma_max is required")
+        c = np.ascontiguousarray(np.asarray(centres, dtype=np.float32).reshape(-1, 3))
+        self._cx = np.ascontiguousarray(c[:, 0])
+        self._cy = np.ascontiguousarray(c[:, 1])
+        self._cz = np.ascontiguousarray(c[:, 2])
+        self._sens = np.ascontiguousarray(np.asarray(sensors, dtype=np.float32).reshape(-1, 3))
+        fp = ctypes.POINTER(ctypes.c_float)
+        g = _lib.Geometry()
+        g.n_kernels = c.shape[0]
+        g.cx = self._cx.ctypes.data_as(fp)
+        g.cy = self._cy.ctypes.data_as(fp)
+        g.cz = self._cz.ctypes.data_as(fp)
+        g.n_sensors = self._sens.shape[0]
+        g.sensors = self._sens.ctypes.data_as(fp)
+        g.n_samples = int(n_samples)
+        g.dt = float(dt)
+        g.t0 = float(t0)
+        g.c_sound = float(c_sound)
+        g.n_sigma = float(n_sigma)
+        g.sigma_max = float(sigma_max)
+        g.fwd_tile = int(fwd_tile)
+        g.adj_tile = int(adj_tile)
+        g.fwd_waves = int(fwd_waves)
+        self.device = torch.device(device) if device is not None else torch.device(
+            "cuda", torch.cuda.current_device())
+        self._h = ctypes.c_void_p()
+        check(_lib.gpair_plan_create(ctypes.byref(g), ctypes.byref(self._h)), "gpair_plan_create")
+        nbytes = ctypes.c_size_t()
+        check(_lib.gpair_plan_workspace_size(self._h, ctypes.byref(nbytes)),
+              "gpair_plan_workspace_size")
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+            check(_lib.gpair_plan_bind_workspace(self._h, ctypes.c_void_p(self.workspace.data_ptr()),
+                                                 nbytes.value, _stream()),
+                  "gpair_plan_bind_workspace")
+        self.n_kernels = int(c.shape[0])
+        self.n_sensors = int(self._sens.shape[0])
+        self.n_samples = int(n_samples)
+        self.dt, self.t0, self.c_sound = float(dt), float(t0), float(c_sound)
+        self.n_sigma, self.sigma_max = float(n_sigma), float(sigma_max)
+
+    # -- lifetime --------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.gpair_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- information ------------------------------------------------------
+    def info(self):
+        i = _lib.PlanInfo()
+        check(_lib.gpair_plan_get_info(self._h, ctypes.byref(i)), "gpair_plan_get_info")
+        return {f: getattr(i, f) for f, _ in i._fields_}
+
+    # -- operators --------------------------------------------------------
+    def forward(self, A, sigma, out=None):
+        """y (N_d, N_t) float32 = A(x; sigma)."""
+        M = self.n_kernels
+        pa = _dev(A, "A", M, device=self.device)
+        ps = _dev(sigma, "sigma", M, device=self.device)
+        if out is None:
+            out = torch.empty((self.n_sensors, self.n_samples), dtype=torch.float32,
+                              device=self.device)
+        py = _dev(out, "y", self.n_sensors * self.n_samples, device=self.device)
+        check(_lib.gpair_forward(self._h, pa, ps, py, _stream()), "gpair_forward")
+        return out
+
+    def adjoint(self, A, sigma, delta, want_sigma=True, out_A=None, out_sigma=None):
+        """(gA, gsigma) float32 [M]; gsigma is None unless want_sigma."""
+        M = self.n_kernels
+        ps = _dev(sigma, "sigma", M, device=self.device)
+        pd = _dev(delta, "delta", self.n_sensors * self.n_samples, device=self.device)
+        pa = _dev(A, "A", M, device=self.device) if (want_sigma or A is not None) else None
+        gA = out_A if out_A is not None else torch.empty(M, dtype=torch.float32, device=self.device)
+        pga = _dev(gA, "gA", M, device=self.device)
+        gS = None
+        pgs = None
+        if want_sigma:
+            gS = out_sigma if out_sigma is not None else torch.empty(M, dtype=torch.float32,
+                                                                     device=self.device)
+            pgs = _dev(gS, "gsigma", M, device=self.device)
+        check(_lib.gpair_adjoint(self._h, pa, ps, pd, pga, pgs, _stream()), "gpair_adjoint")
+        return gA, gS
+
+    def residual(self, y, b, scale=1.0, delta=None):
+        """norms (2,) float64 on device = (sum (y-b)^2, sum b^2); writes
+        delta = scale (y - b) when `delta` is given (may be y itself)."""
+        n = self.n_sensors * self.n_samples
+        py = _dev(y, "y", n, device=self.device)
+        pb = _dev(b, "b", n, device=self.device)
+        pdl = _dev(delta, "delta", n, device=self.device) if delta is not None else None
+        norms = torch.empty(2, dtype=torch.float64, device=self.device)
+        pn = _dev(norms, "norms", 2, dtype=torch.float64, device=self.device)
+        check(_lib.gpair_residual(self._h, py, pb, float(scale), pdl, pn, _stream()),
+              "gpair_residual")
+        return norms
+
+    def sigma_violations(self):
+        n = ctypes.c_int64()
+        check(_lib.gpair_sigma_violations(self._h, ctypes.byref(n), _stream()),
+              "gpair_sigma_violations")
+        return int(n.value)
+
+    # -- timing -----------------------------------------------------------
+    def set_timing(self, enable=True):
+        check(_lib.gpair_plan_set_timing(self._h, 1 if enable else 0), "gpair_plan_set_timing")
+
+    def kernel_times(self, which):
+        """Durations (ms) of the main kernel of the recorded calls of kind
+        'forward' or 'adjoint' since the last read (at most 64, oldest first)."""
+        w = {"forward": _lib.TIMER_FORWARD, "adjoint": _lib.TIMER_ADJOINT}[which]
+        buf = (ctypes.c_float * _lib.TIMER_SLOTS)()
+        n = ctypes.c_int32()
+        check(_lib.gpair_plan_kernel_times(self._h, w, buf, _lib.TIMER_SLOTS, ctypes.byref(n)),
+              "gpair_plan_kernel_times")
+        return [float(buf[i]) for i in range(min(n.value, _lib.TIMER_SLOTS))]
+
+    # -- solver -----------------------------------------------------------
+    def solve(self, b, A, sigma, method="adam", max_iters=100, tol=0.0, step=0.0,
+              lr_A=1e-2, lr_sigma=0.0, beta1=0.9, beta2=0.999, eps=1e-8,
+              learn_sigma=False, sigma_lo=None, sigma_hi=None, a_lo=0.0,
+              a_hi=float("inf"), check_every=1):
+        """Run gpair_solve in place on A (and sigma).  Returns a dict report."""
+        o = _lib.SolveOpts()
+        o.method = {"pgd": _lib.SOLVE_PGD, "adam": _lib.SOLVE_ADAM}[method]
+        o.max_iters = int(max_iters)
+        o.tol = float(tol)
+        o.step = float(step)
+        o.lr_A = float(lr_A)
+        o.lr_sigma = float(lr_sigma)
+        o.beta1, o.beta2, o.eps = float(beta1), float(beta2), float(eps)
+        o.learn_sigma = 1 if learn_sigma else 0
+        o.sigma_lo = float(sigma_lo if sigma_lo is not None else 0.5 * self.sigma_max)
+        o.sigma_hi = float(sigma_hi if sigma_hi is not None else self.sigma_max)
+        o.a_lo, o.a_hi = float(a_lo), float(a_hi)
+        o.check_every = int(check_every)
+        nbytes = ctypes.c_size_t()
+        check(_lib.gpair_solve_workspace_size(self._h, ctypes.byref(o), ctypes.byref(nbytes)),
+              "gpair_solve_workspace_size")
+        ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        M = self.n_kernels
+        pb = _dev(b, "b", self.n_sensors * self.n_samples, device=self.device)
+        pa = _dev(A, "A", M, device=self.device)
+        ps = _dev(sigma, "sigma", M, device=self.device)
+        hist = (ctypes.c_double * (max_iters + 1))()
+        rep = _lib.SolveReport()
+        rep.history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+        st = check(_lib.gpair_solve(self._h, pb, pa, ps, ctypes.byref(o),
+                                    ctypes.c_void_p(ws.data_ptr()), nbytes.value,
+                                    ctypes.byref(rep), _stream()), "gpair_solve")
+        return {"status": _lib.STATUS[st], "iters": rep.iters, "rel_residual": rep.rel_residual,
+                "seconds": rep.seconds, "converged": bool(rep.converged),
+                "history": [h for h in hist[: max_iters + 1]]}
+
+
+def pgd_update(x, g, step, lo=0.0, hi=float("inf")):
+    n = x.numel()
+    check(_lib.gpair_pgd_update(n, _dev(x, "x", n), _dev(g, "g", n), float(step), float(lo),
+                                float(hi), _stream()), "gpair_pgd_update")
+    return x
+
+
+def adam_update(x, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, grad_scale=1.0,
+                lo=float("-inf"), hi=float("inf")):
+    n = x.numel()
+    check(_lib.gpair_adam_update(n, _dev(x, "x", n), _dev(g, "g", n), _dev(m, "m", n),
+                                 _dev(v, "v", n), float(grad_scale), float(lr), float(beta1),
+                                 float(beta2), float(eps), int(t), float(lo), float(hi),
+                                 _stream()), "gpair_adam_update")
+    return x
+
+
+__all__ = ["Plan", "pgd_update", "adam_update", "GpairError"]

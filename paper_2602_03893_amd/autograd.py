@@ -1,0 +1,35 @@
+"""torch.autograd.Function over the HIP operators.
+
+Forward: y = A(x; sigma) (gpair_forward).  Backward: the hand-written adjoint
+(gpair_adjoint) gives dL/dA and dL/dsigma from dL/dy; the taps are recomputed
+in the backward, so only A and sigma are saved (no per-tap intermediates and
+no copy of y).  The adjoint is the transpose of the forward (arXiv 2602.03893,
+Methods, "Adjoint Operator" subsection) and the sigma-gradient the derivative
+of Eq. (single_forward) with respect to sigma.
+"""
+import torch
+
+
+class GpairForward(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, A, sigma, plan):
+        A = A.contiguous()
+        sigma = sigma.contiguous()
+        ctx.plan = plan
+        ctx.save_for_backward(A, sigma)
+        return plan.forward(A, sigma)
+
+    @staticmethod
+    def backward(ctx, grad_y):
+        A, sigma = ctx.saved_tensors
+        want_a = ctx.needs_input_grad[0]
+        want_s = ctx.needs_input_grad[1]
+        if not (want_a or want_s):
+            return None, None, None
+        gA, gS = ctx.plan.adjoint(A, sigma, grad_y.contiguous(), want_sigma=want_s)
+        return (gA if want_a else None), (gS if want_s else None), None
+
+
+def gpair_forward(A, sigma, plan):
+    """Differentiable y = A(x; sigma) for the given bound Plan."""
+    return GpairForward.apply(A, sigma, plan)

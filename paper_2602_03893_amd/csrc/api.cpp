@@ -1,0 +1,243 @@
+// api.cpp -- extern "C" entry points of libgpair (declared in include/gpair.h).
+// Host-side argument validation, then kernel launches on the caller's stream.
+// No C++ exception crosses the boundary.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "gpair_internal.h"
+
+using namespace gpair;
+
+namespace {
+
+gpair_status hip_status(hipError_t e) { return e == hipSuccess ? GPAIR_OK : GPAIR_ERR_HIP; }
+
+bool bound(const gpair_plan_s *p) { return p && p->ws; }
+
+}  // namespace
+
+extern "C" {
+
+const char *gpair_status_string(gpair_status st) {
+  switch (st) {
+    case GPAIR_OK: return "GPAIR_OK";
+    case GPAIR_NOT_CONVERGED: return "GPAIR_NOT_CONVERGED";
+    case GPAIR_ERR_INVALID_ARG: return "GPAIR_ERR_INVALID_ARG";
+    case GPAIR_ERR_NEAR_FIELD: return "GPAIR_ERR_NEAR_FIELD";
+    case GPAIR_ERR_NONFINITE: return "GPAIR_ERR_NONFINITE";
+    case GPAIR_ERR_HIP: return "GPAIR_ERR_HIP";
+    case GPAIR_ERR_WORKSPACE: return "GPAIR_ERR_WORKSPACE";
+    case GPAIR_ERR_SIGMA_RANGE: return "GPAIR_ERR_SIGMA_RANGE";
+  }
+  return "GPAIR_UNKNOWN_STATUS";
+}
+
+int gpair_abi_version(void) { return GPAIR_ABI_VERSION; }
+
+gpair_status gpair_plan_create(const gpair_geometry *g, gpair_plan *out) {
+  if (!out) return GPAIR_ERR_INVALID_ARG;
+  *out = nullptr;
+  gpair_plan_s *p = nullptr;
+  try {
+    p = new gpair_plan_s();
+    p->ws = nullptr;
+    p->ws_bytes = 0;
+    p->timing = 0;
+    for (int w = 0; w < 2; ++w) {
+      p->ev_head[w] = p->ev_count[w] = 0;
+      for (int i = 0; i < GPAIR_TIMER_SLOTS; ++i) p->ev_start[w][i] = p->ev_stop[w][i] = nullptr;
+    }
+    gpair_status st = build_plan(g, p);
+    if (st != GPAIR_OK) {
+      delete p;
+      return st;
+    }
+  } catch (const std::bad_alloc &) {
+    delete p;
+    return GPAIR_ERR_INVALID_ARG;
+  } catch (...) {
+    delete p;
+    return GPAIR_ERR_INVALID_ARG;
+  }
+  *out = p;
+  return GPAIR_OK;
+}
+
+gpair_status gpair_plan_workspace_size(gpair_plan p, size_t *bytes) {
+  if (!p || !bytes) return GPAIR_ERR_INVALID_ARG;
+  *bytes = p->lay.total;
+  return GPAIR_OK;
+}
+
+gpair_status gpair_plan_bind_workspace(gpair_plan p, void *workspace, size_t workspace_bytes,
+                                       gpair_stream stream) {
+  if (!p) return GPAIR_ERR_INVALID_ARG;
+  if (!workspace || workspace_bytes < p->lay.total || ((uintptr_t)workspace & 255u))
+    return GPAIR_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  char *ws = (char *)workspace;
+  const HostTables &h = p->host;
+  hipError_t e = hipSuccess;
+  auto up = [&](size_t off, const void *src, size_t n) {
+    if (e == hipSuccess && n) e = hipMemcpyAsync(ws + off, src, n, hipMemcpyHostToDevice, s);
+  };
+  up(p->lay.sens, h.sens.data(), h.sens.size() * sizeof(double));
+  up(p->lay.kgeo, h.kgeo.data(), h.kgeo.size() * sizeof(double));
+  up(p->lay.perm, h.perm.data(), h.perm.size() * sizeof(int32_t));
+  up(p->lay.ftiles, h.ftiles.data(), h.ftiles.size() * sizeof(TileInfo));
+  up(p->lay.atiles, h.atiles.data(), h.atiles.size() * sizeof(TileInfo));
+  static const unsigned long long zeros[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  up(p->lay.counters, zeros, sizeof(zeros));
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return GPAIR_ERR_HIP;
+  p->ws = ws;
+  p->ws_bytes = workspace_bytes;
+  return GPAIR_OK;
+}
+
+void gpair_plan_destroy(gpair_plan p) {
+  if (!p) return;
+  for (int w = 0; w < 2; ++w)
+    for (int i = 0; i < GPAIR_TIMER_SLOTS; ++i) {
+      if (p->ev_start[w][i]) (void)hipEventDestroy(p->ev_start[w][i]);
+      if (p->ev_stop[w][i]) (void)hipEventDestroy(p->ev_stop[w][i]);
+    }
+  delete p;
+}
+
+gpair_status gpair_plan_get_info(gpair_plan p, gpair_plan_info *info) {
+  if (!p || !info) return GPAIR_ERR_INVALID_ARG;
+  info->n_kernels = p->M;
+  info->n_sensors = p->Nd;
+  info->n_samples = p->Nt;
+  info->fwd_tile = p->fwd_tile;
+  info->adj_tile = p->adj_tile;
+  info->fwd_waves = p->fwd_waves;
+  info->fwd_tiles = (int64_t)p->host.ftiles.size();
+  info->adj_tiles = (int64_t)p->host.atiles.size();
+  info->fwd_segment = p->Lf;
+  info->adj_segment = p->La;
+  info->max_taps = p->ntap_max;
+  info->max_tile_radius = p->max_rho;
+  info->min_distance = p->min_dist;
+  info->workspace_bytes = p->lay.total;
+  return GPAIR_OK;
+}
+
+static void timer_begin(gpair_plan p, int which, hipStream_t s) {
+  if (p->timing) (void)hipEventRecord(p->ev_start[which][p->ev_head[which]], s);
+}
+static void timer_end(gpair_plan p, int which, hipStream_t s) {
+  if (!p->timing) return;
+  (void)hipEventRecord(p->ev_stop[which][p->ev_head[which]], s);
+  p->ev_head[which] = (p->ev_head[which] + 1) % GPAIR_TIMER_SLOTS;
+  if (p->ev_count[which] < GPAIR_TIMER_SLOTS) ++p->ev_count[which];
+}
+
+gpair_status gpair_forward(gpair_plan p, const float *A, const float *sigma, float *y,
+                           gpair_stream stream) {
+  if (!bound(p) || !A || !sigma || !y) return GPAIR_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_prep(p, A, sigma, s);
+  if (e == hipSuccess) e = launch_fill(y, (int64_t)p->Nd * p->Nt, 0.0f, s);
+  if (e != hipSuccess) return GPAIR_ERR_HIP;
+  timer_begin(p, GPAIR_TIMER_FORWARD, s);
+  e = launch_forward(p, y, s);
+  timer_end(p, GPAIR_TIMER_FORWARD, s);
+  return hip_status(e);
+}
+
+gpair_status gpair_adjoint(gpair_plan p, const float *A, const float *sigma,
+                           const float *delta, float *gA, float *gsigma,
+                           gpair_stream stream) {
+  if (!bound(p) || !sigma || !delta || !gA) return GPAIR_ERR_INVALID_ARG;
+  if (gsigma && !A) return GPAIR_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_prep(p, A, sigma, s);
+  if (e != hipSuccess) return GPAIR_ERR_HIP;
+  timer_begin(p, GPAIR_TIMER_ADJOINT, s);
+  e = launch_adjoint(p, delta, gA, gsigma, s);
+  timer_end(p, GPAIR_TIMER_ADJOINT, s);
+  return hip_status(e);
+}
+
+gpair_status gpair_sigma_violations(gpair_plan p, int64_t *count, gpair_stream stream) {
+  if (!bound(p) || !count) return GPAIR_ERR_INVALID_ARG;
+  unsigned long long v = 0;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(&v, ws_counters(p), sizeof(v), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return GPAIR_ERR_HIP;
+  *count = (int64_t)v;
+  return GPAIR_OK;
+}
+
+gpair_status gpair_residual(gpair_plan p, const float *y, const float *b, float scale,
+                            float *delta, double *norms, gpair_stream stream) {
+  if (!bound(p) || !y || !b || !norms || !std::isfinite(scale)) return GPAIR_ERR_INVALID_ARG;
+  return hip_status(launch_residual(p, y, b, scale, delta, norms, (hipStream_t)stream));
+}
+
+gpair_status gpair_pgd_update(int64_t n, float *x, const float *g, float step, float lo,
+                              float hi, gpair_stream stream) {
+  if (n < 0 || (n > 0 && (!x || !g)) || !std::isfinite(step) || std::isnan(lo) ||
+      std::isnan(hi) || lo > hi)
+    return GPAIR_ERR_INVALID_ARG;
+  if (n == 0) return GPAIR_OK;
+  return hip_status(launch_pgd(n, x, g, step, lo, hi, (hipStream_t)stream));
+}
+
+gpair_status gpair_adam_update(int64_t n, float *x, const float *g, float *m, float *v,
+                               float grad_scale, float lr, float beta1, float beta2,
+                               float eps, int32_t t, float lo, float hi,
+                               gpair_stream stream) {
+  if (n < 0 || (n > 0 && (!x || !g || !m || !v)) || t < 1 || !std::isfinite(grad_scale) ||
+      !std::isfinite(lr) || !(beta1 >= 0.0f && beta1 < 1.0f) ||
+      !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f) || std::isnan(lo) ||
+      std::isnan(hi) || lo > hi)
+    return GPAIR_ERR_INVALID_ARG;
+  if (n == 0) return GPAIR_OK;
+  return hip_status(launch_adam(n, x, g, m, v, grad_scale, lr, beta1, beta2, eps, t, lo, hi,
+                                (hipStream_t)stream));
+}
+
+gpair_status gpair_plan_set_timing(gpair_plan p, int enable) {
+  if (!p) return GPAIR_ERR_INVALID_ARG;
+  if (enable) {
+    for (int w = 0; w < 2; ++w)
+      for (int i = 0; i < GPAIR_TIMER_SLOTS; ++i) {
+        if (!p->ev_start[w][i] && hipEventCreate(&p->ev_start[w][i]) != hipSuccess)
+          return GPAIR_ERR_HIP;
+        if (!p->ev_stop[w][i] && hipEventCreate(&p->ev_stop[w][i]) != hipSuccess)
+          return GPAIR_ERR_HIP;
+      }
+  }
+  p->timing = enable ? 1 : 0;
+  p->ev_head[0] = p->ev_head[1] = p->ev_count[0] = p->ev_count[1] = 0;
+  return GPAIR_OK;
+}
+
+gpair_status gpair_plan_kernel_times(gpair_plan p, int which, float *ms, int32_t capacity,
+                                     int32_t *count) {
+  if (!p || !count || capacity < 0 || (capacity > 0 && !ms) ||
+      (which != GPAIR_TIMER_FORWARD && which != GPAIR_TIMER_ADJOINT) || !p->timing)
+    return GPAIR_ERR_INVALID_ARG;
+  const int n = p->ev_count[which];
+  const int first = (p->ev_head[which] - n + GPAIR_TIMER_SLOTS) % GPAIR_TIMER_SLOTS;
+  if (n > 0) {
+    const int last = (p->ev_head[which] - 1 + GPAIR_TIMER_SLOTS) % GPAIR_TIMER_SLOTS;
+    if (hipEventSynchronize(p->ev_stop[which][last]) != hipSuccess) return GPAIR_ERR_HIP;
+  }
+  for (int i = 0; i < n && i < capacity; ++i) {
+    const int slot = (first + i) % GPAIR_TIMER_SLOTS;
+    if (hipEventElapsedTime(ms + i, p->ev_start[which][slot], p->ev_stop[which][slot]) !=
+        hipSuccess)
+      return GPAIR_ERR_HIP;
+  }
+  *count = n;
+  p->ev_count[which] = 0;
+  return GPAIR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,123 @@
+// gpair_internal.h -- data layout shared by the host planner, the C ABI layer
+// and the gfx950 kernels.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "gpair.h"
+
+namespace gpair {
+
+// Bounding sphere and kernel range of one tile (a compact spatial block of
+// kernels, consecutive in the plan's permuted kernel order).
+struct alignas(16) TileInfo {
+  double cx, cy, cz;  // sphere centre (m)
+  double rho;         // sphere radius (m): every member is within rho
+  int32_t start;      // first member in permuted order
+  int32_t count;      // number of members (<= the tile size)
+  int32_t pad0, pad1;
+};
+static_assert(sizeof(TileInfo) == 48, "TileInfo layout");
+
+// Per-kernel coefficients, rebuilt on every operator call from (A, sigma).
+// With Delta = v*dt and c = -log2(e) / (2 sigma^2):
+//   exp(-d^2/(2 sigma^2)) = exp2(c d^2);
+//   the ratio of consecutive taps (d -> d - Delta) is q(d) = exp2(k2 + k1 d)
+//   with k1 = -2 c Delta, k2 = c Delta^2, and q itself is multiplied by
+//   rq = exp2(2 c Delta^2) from one tap to the next.
+struct alignas(32) KernelRec {
+  float amp;    // A_k
+  float c;      // -log2(e) / (2 sigma_k^2)
+  float k1;     // -2 c Delta
+  float k2;     // c Delta^2
+  float rq;     // exp2(2 c Delta^2)
+  int32_t ntap; // floor(2 h) + 1: most samples a window can hold
+  double h;     // n_sigma sigma_k / Delta: window half-width in samples
+};
+static_assert(sizeof(KernelRec) == 32, "KernelRec layout");
+
+constexpr int kWave = 64;
+constexpr int kAdjSensorsPerStage = 64; // sensors staged per LDS refill
+constexpr int kMaxSegmentBytes = 63 * 1024; // dynamic LDS per workgroup (64 KiB less static use)
+constexpr int kResidualBlocks = 1024;
+constexpr int kXcds = 8;                // MI355X: 8 accelerator dies
+
+// Offsets (bytes) of each table inside the plan workspace.
+struct WorkspaceLayout {
+  size_t sens, kgeo, perm, ftiles, atiles, krec, counters, partials, total;
+};
+
+struct HostTables {
+  std::vector<double> sens;      // [Nd][4]
+  std::vector<double> kgeo;      // [M][4] permuted centres
+  std::vector<int32_t> perm;     // [M] permuted index -> caller index
+  std::vector<TileInfo> ftiles;  // forward tiles
+  std::vector<TileInfo> atiles;  // adjoint tiles
+};
+
+}  // namespace gpair
+
+struct gpair_plan_s {
+  // geometry constants
+  int64_t M;
+  int32_t Nd, Nt;
+  double dt, t0, v, nsig, sigma_max;
+  double vdt, inv_vdt, t0_over_dt, hmax;
+  int32_t ntap_max;
+  // tiling
+  int32_t fwd_tile, adj_tile;
+  int32_t fwd_waves;  // waves (sensor groups of 64) per forward workgroup
+  int32_t Lf, La;     // samples per forward / adjoint LDS segment
+  double max_rho, min_dist;
+  gpair::HostTables host;
+  gpair::WorkspaceLayout lay;
+  // bound workspace (device)
+  char *ws;
+  size_t ws_bytes;
+  // timing: per kind (forward, adjoint) a ring of event pairs
+  int timing;
+  hipEvent_t ev_start[2][GPAIR_TIMER_SLOTS];
+  hipEvent_t ev_stop[2][GPAIR_TIMER_SLOTS];
+  int ev_head[2];
+  int ev_count[2];
+};
+
+namespace gpair {
+
+// Kernel launchers (operators.hip, vector_ops.hip).  All return hipSuccess or
+// the launch error.
+hipError_t launch_prep(const gpair_plan_s *p, const float *A, const float *sigma,
+                       hipStream_t s);
+hipError_t launch_fill(float *x, int64_t n, float value, hipStream_t s);
+hipError_t launch_forward(const gpair_plan_s *p, float *y, hipStream_t s);
+hipError_t launch_adjoint(const gpair_plan_s *p, const float *delta, float *gA,
+                          float *gsigma, hipStream_t s);
+hipError_t launch_residual(const gpair_plan_s *p, const float *y, const float *b,
+                           float scale, float *delta, double *norms,
+                           hipStream_t s);
+hipError_t launch_pgd(int64_t n, float *x, const float *g, float step, float lo,
+                      float hi, hipStream_t s);
+hipError_t launch_adam(int64_t n, float *x, const float *g, float *m, float *v,
+                       float grad_scale, float lr, float beta1, float beta2,
+                       float eps, int32_t t, float lo, float hi, hipStream_t s);
+
+// Workspace pointers of a bound plan.
+inline double *ws_sens(const gpair_plan_s *p) { return (double *)(p->ws + p->lay.sens); }
+inline double *ws_kgeo(const gpair_plan_s *p) { return (double *)(p->ws + p->lay.kgeo); }
+inline int32_t *ws_perm(const gpair_plan_s *p) { return (int32_t *)(p->ws + p->lay.perm); }
+inline TileInfo *ws_ftiles(const gpair_plan_s *p) { return (TileInfo *)(p->ws + p->lay.ftiles); }
+inline TileInfo *ws_atiles(const gpair_plan_s *p) { return (TileInfo *)(p->ws + p->lay.atiles); }
+inline KernelRec *ws_krec(const gpair_plan_s *p) { return (KernelRec *)(p->ws + p->lay.krec); }
+inline unsigned long long *ws_counters(const gpair_plan_s *p) {
+  return (unsigned long long *)(p->ws + p->lay.counters);
+}
+inline double *ws_partials(const gpair_plan_s *p) { return (double *)(p->ws + p->lay.partials); }
+
+// Host planner (plan.cpp).
+gpair_status build_plan(const gpair_geometry *g, gpair_plan_s *p);
+WorkspaceLayout layout_for(int64_t M, int32_t Nd, size_t nft, size_t nat);
+
+}  // namespace gpair

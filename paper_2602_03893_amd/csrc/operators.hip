@@ -1,0 +1,436 @@
+// operators.hip -- gfx950 kernels of the direct GPAIR operators.
+//
+// Forward (arXiv 2602.03893, Eq. (single_forward) summed over kernels, inside
+// the n_sigma window that follows it):
+//   y_j[n] = sum_k [|d| <= n_sigma sigma_k] A_k/(2 r_jk) d exp(-d^2/(2 sigma_k^2)),
+//   d = r_jk - v (t0 + n dt).
+// Adjoint: its transpose, plus the sigma-derivative of Eq. (single_forward).
+//
+// Work decomposition (VALU-bound; no MFMA: nothing here is a contraction).
+//  * Pair stage, float64: r = |s - c| (float64 difference of float32
+//    coordinates, float32 rsq seed + one float64 Newton step), pulse centre
+//    in samples nc = (r - v t0)/(v dt), first in-window sample lo =
+//    ceil(nc - h) with h = n_sigma sigma / (v dt).  Window membership is
+//    therefore decided in float64, as in the float64 reference.
+//  * Tap stage, float32: d_i = d_0 - i Delta, and the Gaussian factor by the
+//    exact recurrence e_{i+1} = e_i q_i, q_{i+1} = q_i rq (two exp2 per pair
+//    instead of one per tap).
+//  * Forward: one wave = one tile of kernels x 64 sensors; lane = sensor, the
+//    kernel loop is wave-uniform (kernel data in scalar registers).  Each lane
+//    owns one LDS column: the trace segment of its sensor over the tile's time
+//    shell, so taps accumulate by plain read-modify-write without bank
+//    conflicts.  At the end the segments are added to y with one coalesced
+//    float atomic per sample (tile-sensor partial sums), not one per tap.
+//  * Adjoint: one workgroup = one tile of kernels; lane = kernel, the sensor
+//    loop is uniform.  For each stage of 64 sensors the residual over the
+//    tile's time shell is staged in LDS; every lane gathers its taps from it.
+//    Per-lane sums go from float32 (within a stage) to float64 (across
+//    stages); no atomics.
+//  * Blocks are remapped so that each of the 8 XCDs works on a contiguous
+//    range of tiles (its L2 then holds that region's kernel records and the
+//    matching residual rows).
+#include "gpair_internal.h"
+
+namespace gpair {
+namespace {
+
+constexpr double kLog2e = 1.4426950408889634074;
+
+__device__ __forceinline__ int64_t xcd_logical_block(int64_t nlogical) {
+  const int64_t per = (nlogical + kXcds - 1) / kXcds;
+  const int64_t b = blockIdx.x;
+  return (b % kXcds) * per + b / kXcds;
+}
+
+inline unsigned int xcd_grid(int64_t nlogical) {
+  const int64_t per = (nlogical + kXcds - 1) / kXcds;
+  return (unsigned int)(per * kXcds);
+}
+
+// ---------------------------------------------------------------------------
+// Per-call coefficient records (permuted order).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void prep_kernel(
+    const float *__restrict__ A, const float *__restrict__ sigma,
+    const int32_t *__restrict__ perm, KernelRec *__restrict__ rec, int64_t M,
+    double vdt, double nsig, double smax_eff, unsigned long long *viol) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= M) return;
+  const int32_t k = perm[i];
+  const float a = A ? A[k] : 0.0f;
+  double s = (double)sigma[k];
+  if (!(s > 0.0 && s <= smax_eff)) {
+    atomicAdd(viol, 1ULL);
+    s = (s > smax_eff) ? smax_eff : ((s > 0.0) ? s : smax_eff);
+  }
+  const double c = -kLog2e / (2.0 * s * s);
+  KernelRec r;
+  r.amp = a;
+  r.c = (float)c;
+  r.k1 = (float)(-2.0 * c * vdt);
+  r.k2 = (float)(c * vdt * vdt);
+  r.rq = (float)exp2(2.0 * c * vdt * vdt);
+  r.h = nsig * s / vdt;
+  r.ntap = (int32_t)floor(2.0 * r.h) + 1;
+  rec[i] = r;
+}
+
+// ---------------------------------------------------------------------------
+// Pair stage shared by both operators (float64 distance and window).
+// ---------------------------------------------------------------------------
+struct PairTerms {
+  double fr;    // nc - lo in (h - 1, h]: offset of the first tap, in samples
+  int lo;       // first in-window sample index
+  float rinv;   // 1/r (float32 rsq seed)
+};
+
+__device__ __forceinline__ PairTerms pair_terms(double sx, double sy, double sz,
+                                                double cx, double cy, double cz,
+                                                double h, double inv_vdt,
+                                                double t0_over_dt) {
+  const double ex = sx - cx, ey = sy - cy, ez = sz - cz;
+  const double r2 = fma(ez, ez, fma(ey, ey, ex * ex));
+  const float y0 = __builtin_amdgcn_rsqf((float)r2);
+  const double y0d = (double)y0;
+  const double r0 = r2 * y0d;                  // ~r to float32 accuracy
+  const double res = fma(-r0, r0, r2);         // r2 - r0^2
+  const double r = fma(res, 0.5 * y0d, r0);    // one Newton step: ~1e-15 rel
+  const double nc = fma(r, inv_vdt, -t0_over_dt);
+  const double lo = ceil(nc - h);
+  PairTerms t;
+  t.fr = nc - lo;
+  t.lo = (int)lo;
+  t.rinv = y0;
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// Forward.
+// ---------------------------------------------------------------------------
+struct FwdArgs {
+  const double4 *__restrict__ sens;
+  const double4 *__restrict__ kgeo;
+  const KernelRec *__restrict__ krec;
+  const TileInfo *__restrict__ tiles;
+  float *__restrict__ y;
+  int64_t nlogical;
+  int32_t Nd, Nt, nsg, nsgw, L;
+  double inv_vdt, t0_over_dt, hmax, vdt;
+};
+
+// Add the taps of one pair into a lane's segment column: 2P samples from p
+// (stride 64 floats).  Taps 0 .. ntap-2 are in the window for every lane,
+// tap ntap-1 only where last_ok, and a tap ntap (when 2P = ntap + 1) is
+// padding.  ntap is 2P - 1 or 2P.  All reads are issued before the
+// arithmetic so their latency overlaps it.
+template <int P>
+__device__ __forceinline__ void taps_rmw(float *p, float f, float q, float d, float rq,
+                                         float vdt, int ntap, bool last_ok) {
+  float old[2 * P];
+#pragma unroll
+  for (int i = 0; i < 2 * P; ++i) old[i] = p[i * kWave];
+  float t[2 * P];
+#pragma unroll
+  for (int i = 0; i < 2 * P; ++i) {
+    t[i] = f * d;
+    d -= vdt;
+    f *= q;
+    q *= rq;
+  }
+  const bool even = ntap == 2 * P;
+  if (!(even || last_ok)) t[2 * P - 2] = 0.0f;
+  if (!(even && last_ok)) t[2 * P - 1] = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 2 * P; ++i) p[i * kWave] = old[i] + t[i];
+}
+
+// One workgroup = one tile x WAVES sensor groups of 64.  Every wave owns a
+// private LDS segment [L][64] (sample-major, one column per sensor), so taps
+// accumulate with plain read-modify-write: LDS float atomics are far slower
+// than plain accesses on this chip.  The waves of a workgroup walk the same
+// kernel records, which therefore stream once through the scalar cache.
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * kWave) void forward_kernel(FwdArgs a) {
+  extern __shared__ float seg_all[];  // [WAVES][L][64]
+
+  const int64_t logical = xcd_logical_block(a.nlogical);
+  if (logical >= a.nlogical) return;
+  const int64_t tile = logical / a.nsgw;
+  const int sgw = (int)(logical - tile * a.nsgw);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int sg = sgw * WAVES + wave;
+  const bool wave_live = sg < a.nsg;
+  float *const seg = seg_all + (size_t)wave * a.L * kWave;
+  float *const col = seg + lane;
+
+  const int j = sg * kWave + lane;
+  const double4 s = a.sens[j < a.Nd ? j : a.Nd - 1];
+  const TileInfo T = a.tiles[tile];
+  int nb;
+  {
+    const double dx = s.x - T.cx, dy = s.y - T.cy, dz = s.z - T.cz;
+    const double R = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
+    nb = (int)floor((R - T.rho) * a.inv_vdt - a.t0_over_dt - a.hmax) - 1;
+  }
+
+  if (wave_live) {
+    for (int i = 0; i < a.L; ++i) col[i * kWave] = 0.0f;
+    const float vdt_f = (float)a.vdt;
+    const int kend = T.start + T.count;
+    for (int k = T.start; k < kend; ++k) {
+      const double4 c = a.kgeo[k];
+      const KernelRec r = a.krec[k];
+      const PairTerms pt = pair_terms(s.x, s.y, s.z, c.x, c.y, c.z, r.h, a.inv_vdt,
+                                      a.t0_over_dt);
+      const float d0 = (float)(pt.fr * a.vdt);
+      const bool last_ok = (pt.fr + r.h) >= (double)(r.ntap - 1);
+      // Offset of the first tap in the segment.  By construction of nb and L
+      // every tap index o + i (i < ntap) is at most L - 2; the clamp only
+      // keeps LDS accesses in range if that were ever violated.
+      int o = pt.lo - nb;
+      o = min(max(o, 0), a.L - 1 - r.ntap);
+      float f = (0.5f * r.amp) * pt.rinv * __builtin_amdgcn_exp2f(r.c * d0 * d0);
+      float q = __builtin_amdgcn_exp2f(fmaf(r.k1, d0, r.k2));
+      float d = d0;
+      float *p = col + o * kWave;
+      // ntap is wave-uniform: dispatch to a fully unrolled read-modify-write
+      // of ceil(ntap/2) sample pairs.
+      switch ((r.ntap + 1) >> 1) {
+        case 1: taps_rmw<1>(p, f, q, d, r.rq, vdt_f, r.ntap, last_ok); break;
+        case 2: taps_rmw<2>(p, f, q, d, r.rq, vdt_f, r.ntap, last_ok); break;
+        case 3: taps_rmw<3>(p, f, q, d, r.rq, vdt_f, r.ntap, last_ok); break;
+        case 4: taps_rmw<4>(p, f, q, d, r.rq, vdt_f, r.ntap, last_ok); break;
+        case 5: taps_rmw<5>(p, f, q, d, r.rq, vdt_f, r.ntap, last_ok); break;
+        case 6: taps_rmw<6>(p, f, q, d, r.rq, vdt_f, r.ntap, last_ok); break;
+        case 7: taps_rmw<7>(p, f, q, d, r.rq, vdt_f, r.ntap, last_ok); break;
+        case 8: taps_rmw<8>(p, f, q, d, r.rq, vdt_f, r.ntap, last_ok); break;
+        case 9: taps_rmw<9>(p, f, q, d, r.rq, vdt_f, r.ntap, last_ok); break;
+        default: {
+          const int nfull = r.ntap - 1;
+          for (int i = 0; i < nfull; ++i) {
+            p[i * kWave] += f * d;
+            d -= vdt_f;
+            f *= q;
+            q *= r.rq;
+          }
+          p[nfull * kWave] += last_ok ? f * d : 0.0f;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (!wave_live) return;
+
+  // Flush the wave's 64 rows: lanes walk the samples of one row so that
+  // consecutive lanes add to consecutive addresses of y.
+  for (int row = 0; row < kWave; ++row) {
+    const int jr = sg * kWave + row;
+    if (jr >= a.Nd) break;
+    const int nbr = __builtin_amdgcn_readlane(nb, row);
+    float *yrow = a.y + (int64_t)jr * a.Nt;
+    for (int sidx = lane; sidx < a.L; sidx += kWave) {
+      const int n = nbr + sidx;
+      const float v = seg[sidx * kWave + row];
+      if (n >= 0 && n < a.Nt && v != 0.0f) unsafeAtomicAdd(yrow + n, v);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint.
+// ---------------------------------------------------------------------------
+struct AdjArgs {
+  const double4 *__restrict__ sens;
+  const double4 *__restrict__ kgeo;
+  const KernelRec *__restrict__ krec;
+  const TileInfo *__restrict__ tiles;
+  const int32_t *__restrict__ perm;
+  const float *__restrict__ delta;
+  float *__restrict__ gA;
+  float *__restrict__ gS;
+  int64_t nlogical;
+  int32_t Nd, Nt, L, ntap_max;
+  double inv_vdt, t0_over_dt, hmax, vdt, nsig;
+};
+
+__device__ __forceinline__ int wave_min(int x) {
+  for (int off = 32; off > 0; off >>= 1) x = min(x, __shfl_xor(x, off, kWave));
+  return x;
+}
+__device__ __forceinline__ int wave_max(int x) {
+  for (int off = 32; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off, kWave));
+  return x;
+}
+
+template <int BLOCK, bool SIG>
+__global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjArgs a) {
+  extern __shared__ float stage[];  // [kAdjSensorsPerStage][L]
+  __shared__ int nbs[kAdjSensorsPerStage];
+
+  const int64_t logical = xcd_logical_block(a.nlogical);
+  if (logical >= a.nlogical) return;
+  const TileInfo T = a.tiles[logical];
+  const int t = threadIdx.x;
+  const bool live = t < T.count;
+  const int64_t i = T.start + (live ? t : 0);
+  const double4 c = a.kgeo[i];
+  const KernelRec r = a.krec[i];
+
+  // Taps every lane of the wave has (uniform loop) and the most any has.
+  // A wave with no live lane gets 0 and 0.
+  const int ntail = __builtin_amdgcn_readfirstlane(wave_max(live ? r.ntap : 0));
+  const int nfull = min(ntail, __builtin_amdgcn_readfirstlane(
+                                   wave_min(live ? r.ntap - 1 : 1 << 30)));
+  const float vdt_f = (float)a.vdt;
+  const int omax = a.L - 1 - r.ntap;  // see the forward kernel
+  const int imax = a.L - 1;
+
+  double accA = 0.0, accS = 0.0;
+  for (int j0 = 0; j0 < a.Nd; j0 += kAdjSensorsPerStage) {
+    const int nsb = min(kAdjSensorsPerStage, a.Nd - j0);
+    __syncthreads();
+    if (t < nsb) {
+      const double4 s = a.sens[j0 + t];
+      const double dx = s.x - T.cx, dy = s.y - T.cy, dz = s.z - T.cz;
+      const double R = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
+      nbs[t] = (int)floor((R - T.rho) * a.inv_vdt - a.t0_over_dt - a.hmax) - 1;
+    }
+    __syncthreads();
+    for (int idx = t; idx < nsb * a.L; idx += BLOCK) {
+      const int js = idx / a.L;
+      const int n = nbs[js] + (idx - js * a.L);
+      stage[idx] = (n >= 0 && n < a.Nt) ? a.delta[(int64_t)(j0 + js) * a.Nt + n] : 0.0f;
+    }
+    __syncthreads();
+
+    float pA = 0.0f, pS = 0.0f;
+    for (int js = 0; js < nsb; ++js) {
+      const double4 s = a.sens[j0 + js];
+      const int nb = nbs[js];
+      const PairTerms pt = pair_terms(s.x, s.y, s.z, c.x, c.y, c.z, r.h, a.inv_vdt,
+                                      a.t0_over_dt);
+      const float d0 = (float)(pt.fr * a.vdt);
+      const int nvalid = ((pt.fr + r.h) >= (double)(r.ntap - 1)) ? r.ntap : r.ntap - 1;
+      int o = pt.lo - nb;
+      o = min(max(o, 0), omax);
+      float f = 0.5f * pt.rinv * __builtin_amdgcn_exp2f(r.c * d0 * d0);
+      float q = __builtin_amdgcn_exp2f(fmaf(r.k1, d0, r.k2));
+      float d = d0;
+      const float *dp = stage + js * a.L + o;
+      int it = 0;
+      for (; it < nfull; ++it) {
+        const float pd = dp[it] * f * d;
+        pA += pd;
+        if (SIG) pS = fmaf(pd, d * d, pS);
+        d -= vdt_f;
+        f *= q;
+        q *= r.rq;
+      }
+      const float *srow = stage + js * a.L;
+      for (; it < ntail; ++it) {
+        // lanes past their own window read an in-range sample and drop it
+        const float dl = (it < nvalid) ? srow[min(o + it, imax)] : 0.0f;
+        const float pd = dl * f * d;
+        pA += pd;
+        if (SIG) pS = fmaf(pd, d * d, pS);
+        d -= vdt_f;
+        f *= q;
+        q *= r.rq;
+      }
+    }
+    accA += (double)pA;
+    if (SIG) accS += (double)pS;
+  }
+  if (live) {
+    const int32_t k = a.perm[i];
+    a.gA[k] = (float)accA;
+    if (SIG) {
+      // sigma_k (as clamped by the record builder) from h = n_sigma sigma / Delta.
+      const double sg = r.h * a.vdt / a.nsig;
+      a.gS[k] = (float)(accS * (double)r.amp / (sg * sg * sg));
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_prep(const gpair_plan_s *p, const float *A, const float *sigma,
+                       hipStream_t s) {
+  const int64_t M = p->M;
+  const unsigned int grid = (unsigned int)((M + 255) / 256);
+  prep_kernel<<<grid, 256, 0, s>>>(A, sigma, ws_perm(p), ws_krec(p), M, p->vdt, p->nsig,
+                                   p->sigma_max * (1.0 + 1e-6), ws_counters(p));
+  return hipGetLastError();
+}
+
+hipError_t launch_forward(const gpair_plan_s *p, float *y, hipStream_t s) {
+  FwdArgs a;
+  a.sens = (const double4 *)ws_sens(p);
+  a.kgeo = (const double4 *)ws_kgeo(p);
+  a.krec = ws_krec(p);
+  a.tiles = ws_ftiles(p);
+  a.y = y;
+  a.Nd = p->Nd;
+  a.Nt = p->Nt;
+  a.nsg = (p->Nd + kWave - 1) / kWave;
+  const int W = p->fwd_waves;
+  a.nsgw = (a.nsg + W - 1) / W;
+  a.nlogical = (int64_t)p->host.ftiles.size() * a.nsgw;
+  a.L = p->Lf;
+  a.inv_vdt = p->inv_vdt;
+  a.t0_over_dt = p->t0_over_dt;
+  a.hmax = p->hmax;
+  a.vdt = p->vdt;
+  const size_t lds = (size_t)W * p->Lf * kWave * sizeof(float);
+  const unsigned int grid = xcd_grid(a.nlogical);
+  switch (W) {
+    case 1: forward_kernel<1><<<grid, kWave, lds, s>>>(a); break;
+    case 2: forward_kernel<2><<<grid, 2 * kWave, lds, s>>>(a); break;
+    default: forward_kernel<4><<<grid, 4 * kWave, lds, s>>>(a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint(const gpair_plan_s *p, const float *delta, float *gA,
+                          float *gsigma, hipStream_t s) {
+  AdjArgs a;
+  a.sens = (const double4 *)ws_sens(p);
+  a.kgeo = (const double4 *)ws_kgeo(p);
+  a.krec = ws_krec(p);
+  a.tiles = ws_atiles(p);
+  a.perm = ws_perm(p);
+  a.delta = delta;
+  a.gA = gA;
+  a.gS = gsigma;
+  a.nlogical = (int64_t)p->host.atiles.size();
+  a.Nd = p->Nd;
+  a.Nt = p->Nt;
+  a.L = p->La;
+  a.ntap_max = p->ntap_max;
+  a.inv_vdt = p->inv_vdt;
+  a.t0_over_dt = p->t0_over_dt;
+  a.hmax = p->hmax;
+  a.vdt = p->vdt;
+  a.nsig = p->nsig;
+  const size_t lds = (size_t)p->La * kAdjSensorsPerStage * sizeof(float);
+  const unsigned int grid = xcd_grid(a.nlogical);
+  const bool sig = gsigma != nullptr;
+  switch (p->adj_tile) {
+    case 64:
+      if (sig) adjoint_kernel<64, true><<<grid, 64, lds, s>>>(a);
+      else adjoint_kernel<64, false><<<grid, 64, lds, s>>>(a);
+      break;
+    case 128:
+      if (sig) adjoint_kernel<128, true><<<grid, 128, lds, s>>>(a);
+      else adjoint_kernel<128, false><<<grid, 128, lds, s>>>(a);
+      break;
+    default:
+      if (sig) adjoint_kernel<256, true><<<grid, 256, lds, s>>>(a);
+      else adjoint_kernel<256, false><<<grid, 256, lds, s>>>(a);
+      break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gpair

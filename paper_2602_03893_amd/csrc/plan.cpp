@@ -1,0 +1,322 @@
+// plan.cpp -- host planner: validation, spatial tiling, workspace layout.
+//
+// The direct operator pairs every kernel with every sensor (arXiv 2602.03893,
+// Methods, start of the "Adaptive supersampling alignment" subsection).  The
+// paper precomputes a lookup table of pair distances (Algorithm 1); at 8.4 M
+// kernels x 1024 sensors that table would not fit, so this build computes the
+// distances on the fly and instead precomputes a spatial tiling: kernels are
+// ordered along a Morton curve of the kernel lattice and cut into compact
+// tiles, each described by a bounding sphere.  For a tile and a sensor, every
+// member's pulse arrives inside the time shell [R - rho, R + rho] widened by
+// the window, so one short trace segment per (tile, sensor) holds every tap of
+// the tile: that is the binning by sensor-distance shell the kernels use.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <numeric>
+
+#include "gpair_internal.h"
+
+namespace gpair {
+
+namespace {
+
+inline uint64_t spread3(uint64_t x) {
+  x &= 0x1fffff;  // 21 bits
+  x = (x | (x << 32)) & 0x1f00000000ffffULL;
+  x = (x | (x << 16)) & 0x1f0000ff0000ffULL;
+  x = (x | (x << 8)) & 0x100f00f00f00f00fULL;
+  x = (x | (x << 4)) & 0x10c30c30c30c30c3ULL;
+  x = (x | (x << 2)) & 0x1249249249249249ULL;
+  return x;
+}
+
+inline uint64_t morton3(uint32_t ix, uint32_t iy, uint32_t iz) {
+  return spread3(ix) | (spread3(iy) << 1) | (spread3(iz) << 2);
+}
+
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+int level_for(int64_t tile) {  // smallest l with 8^l >= tile
+  int l = 0;
+  int64_t b = 1;
+  while (b < tile) {
+    b *= 8;
+    ++l;
+  }
+  return l;
+}
+
+// Sorted unique values of one coordinate axis.
+std::vector<float> axis_values(const float *x, int64_t m) {
+  std::vector<float> v(x, x + m);
+  std::sort(v.begin(), v.end());
+  v.erase(std::unique(v.begin(), v.end()), v.end());
+  return v;
+}
+
+struct Keys {
+  std::vector<uint64_t> key;
+  bool lattice = false;
+  double quantum = 0.0;  // point clouds: edge of one quantisation cell (m)
+};
+
+Keys morton_keys(const gpair_geometry *g) {
+  const int64_t m = g->n_kernels;
+  Keys out;
+  out.key.resize(m);
+  std::vector<float> ux = axis_values(g->cx, m), uy = axis_values(g->cy, m),
+                     uz = axis_values(g->cz, m);
+  const double prod = (double)ux.size() * (double)uy.size() * (double)uz.size();
+  if (prod == (double)m && ux.size() < (1u << 21) && uy.size() < (1u << 21) &&
+      uz.size() < (1u << 21)) {
+    // Candidate full lattice: every kernel must map to a distinct lattice node.
+    std::vector<uint8_t> seen((size_t)m, 0);
+    bool ok = true;
+    for (int64_t k = 0; k < m && ok; ++k) {
+      uint32_t ix = (uint32_t)(std::lower_bound(ux.begin(), ux.end(), g->cx[k]) - ux.begin());
+      uint32_t iy = (uint32_t)(std::lower_bound(uy.begin(), uy.end(), g->cy[k]) - uy.begin());
+      uint32_t iz = (uint32_t)(std::lower_bound(uz.begin(), uz.end(), g->cz[k]) - uz.begin());
+      size_t lin = ((size_t)iz * uy.size() + iy) * ux.size() + ix;
+      if (seen[lin]) ok = false;
+      seen[lin] = 1;
+      out.key[k] = morton3(ix, iy, iz);
+    }
+    if (ok) {
+      out.lattice = true;
+      return out;
+    }
+  }
+  // Point cloud: quantise positions on a cubic grid of 2^20 cells per axis.
+  double lo[3] = {ux.front(), uy.front(), uz.front()};
+  double hi[3] = {ux.back(), uy.back(), uz.back()};
+  double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]});
+  double q = ext > 0 ? ext / double((1u << 20) - 1) : 1.0;
+  out.quantum = q;
+  const float *c[3] = {g->cx, g->cy, g->cz};
+  for (int64_t k = 0; k < m; ++k) {
+    uint32_t ii[3];
+    for (int a = 0; a < 3; ++a) {
+      double t = std::floor(((double)c[a][k] - lo[a]) / q);
+      t = std::min(std::max(t, 0.0), double((1u << 20) - 1));
+      ii[a] = (uint32_t)t;
+    }
+    out.key[k] = morton3(ii[0], ii[1], ii[2]);
+  }
+  return out;
+}
+
+// Cut the Morton-ordered kernels into tiles of at most `tile` members that
+// never cross an aligned Morton block of 8^level cells.
+std::vector<TileInfo> make_tiles(const std::vector<uint64_t> &sorted_keys,
+                                 const std::vector<double> &kgeo, int64_t tile,
+                                 int level) {
+  std::vector<TileInfo> tiles;
+  const int64_t m = (int64_t)sorted_keys.size();
+  const int shift = 3 * level;
+  int64_t s = 0;
+  while (s < m) {
+    const uint64_t blk = shift >= 64 ? 0 : (sorted_keys[s] >> shift);
+    int64_t e = s + 1;
+    while (e < m && e - s < tile &&
+           (shift >= 64 ? 0 : (sorted_keys[e] >> shift)) == blk)
+      ++e;
+    TileInfo t{};
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = s; i < e; ++i)
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = std::min(lo[a], kgeo[4 * i + a]);
+        hi[a] = std::max(hi[a], kgeo[4 * i + a]);
+      }
+    t.cx = 0.5 * (lo[0] + hi[0]);
+    t.cy = 0.5 * (lo[1] + hi[1]);
+    t.cz = 0.5 * (lo[2] + hi[2]);
+    double r2 = 0;
+    for (int64_t i = s; i < e; ++i) {
+      double dx = kgeo[4 * i] - t.cx, dy = kgeo[4 * i + 1] - t.cy,
+             dz = kgeo[4 * i + 2] - t.cz;
+      r2 = std::max(r2, dx * dx + dy * dy + dz * dz);
+    }
+    t.rho = std::sqrt(r2) * (1.0 + 1e-12) + 1e-15;
+    t.start = (int32_t)s;
+    t.count = (int32_t)(e - s);
+    tiles.push_back(t);
+    s = e;
+  }
+  return tiles;
+}
+
+double max_rho(const std::vector<TileInfo> &t) {
+  double r = 0;
+  for (const auto &x : t) r = std::max(r, x.rho);
+  return r;
+}
+
+int segment_len(double rho, double inv_vdt, double hmax) {
+  double L = std::ceil(2.0 * rho * inv_vdt + 2.0 * hmax) + 5.0;
+  return L > 1e9 ? 1000000000 : (int)L;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+WorkspaceLayout layout_for(int64_t M, int32_t Nd, size_t nft, size_t nat) {
+  WorkspaceLayout l{};
+  size_t off = 0;
+  l.sens = off;     off = align256(off + (size_t)Nd * 32);
+  l.kgeo = off;     off = align256(off + (size_t)M * 32);
+  l.perm = off;     off = align256(off + (size_t)M * 4);
+  l.ftiles = off;   off = align256(off + nft * sizeof(TileInfo));
+  l.atiles = off;   off = align256(off + nat * sizeof(TileInfo));
+  l.krec = off;     off = align256(off + (size_t)M * sizeof(KernelRec));
+  l.counters = off; off = align256(off + 64);
+  l.partials = off; off = align256(off + (size_t)kResidualBlocks * 2 * sizeof(double) + 64);
+  l.total = off;
+  return l;
+}
+
+gpair_status build_plan(const gpair_geometry *g, gpair_plan_s *p) {
+  if (!g || !g->cx || !g->cy || !g->cz || !g->sensors) return GPAIR_ERR_INVALID_ARG;
+  if (g->n_kernels < 1 || g->n_kernels > (int64_t)INT32_MAX) return GPAIR_ERR_INVALID_ARG;
+  if (g->n_sensors < 1 || g->n_samples < 1) return GPAIR_ERR_INVALID_ARG;
+  const double scal[] = {g->dt, g->t0, g->c_sound, g->n_sigma, g->sigma_max};
+  for (double s : scal)
+    if (!std::isfinite(s)) return GPAIR_ERR_NONFINITE;
+  if (!(g->dt > 0) || !(g->c_sound > 0) || !(g->n_sigma > 0) || !(g->sigma_max > 0))
+    return GPAIR_ERR_INVALID_ARG;
+  if (g->fwd_tile != 0 && (!is_pow2(g->fwd_tile) || g->fwd_tile < 64 || g->fwd_tile > 8192))
+    return GPAIR_ERR_INVALID_ARG;
+  if (g->adj_tile != 0 && g->adj_tile != 64 && g->adj_tile != 128 && g->adj_tile != 256)
+    return GPAIR_ERR_INVALID_ARG;
+  if (g->fwd_waves != 0 && g->fwd_waves != 1 && g->fwd_waves != 2 && g->fwd_waves != 4)
+    return GPAIR_ERR_INVALID_ARG;
+  const int64_t M = g->n_kernels;
+  const int32_t Nd = g->n_sensors;
+  for (int64_t k = 0; k < M; ++k)
+    if (!std::isfinite(g->cx[k]) || !std::isfinite(g->cy[k]) || !std::isfinite(g->cz[k]))
+      return GPAIR_ERR_NONFINITE;
+  for (int64_t j = 0; j < 3 * (int64_t)Nd; ++j)
+    if (!std::isfinite(g->sensors[j])) return GPAIR_ERR_NONFINITE;
+
+  p->M = M;
+  p->Nd = Nd;
+  p->Nt = g->n_samples;
+  p->dt = g->dt;
+  p->t0 = g->t0;
+  p->v = g->c_sound;
+  p->nsig = g->n_sigma;
+  p->sigma_max = g->sigma_max;
+  p->vdt = g->c_sound * g->dt;
+  p->inv_vdt = 1.0 / p->vdt;
+  p->t0_over_dt = g->t0 / g->dt;
+  p->hmax = g->n_sigma * g->sigma_max / p->vdt;
+  if (!(p->hmax < 4096.0)) return GPAIR_ERR_INVALID_ARG;
+  p->ntap_max = (int32_t)std::floor(2.0 * p->hmax) + 1;
+
+  // Spatial order.
+  Keys keys = morton_keys(g);
+  std::vector<int32_t> order((size_t)M);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return keys.key[a] < keys.key[b] || (keys.key[a] == keys.key[b] && a < b);
+  });
+  HostTables &h = p->host;
+  h.perm = order;
+  h.kgeo.assign((size_t)M * 4, 0.0);
+  std::vector<uint64_t> skeys((size_t)M);
+  for (int64_t i = 0; i < M; ++i) {
+    int32_t k = order[i];
+    h.kgeo[4 * i + 0] = g->cx[k];
+    h.kgeo[4 * i + 1] = g->cy[k];
+    h.kgeo[4 * i + 2] = g->cz[k];
+    skeys[i] = keys.key[k];
+  }
+  keys.key.clear();
+  keys.key.shrink_to_fit();
+  h.sens.assign((size_t)Nd * 4, 0.0);
+  for (int32_t j = 0; j < Nd; ++j)
+    for (int a = 0; a < 3; ++a) h.sens[4 * j + a] = g->sensors[3 * j + a];
+
+  // Block level of a tile of T kernels: lattice -> 8^l >= T lattice nodes;
+  // point cloud -> a block edge holding about T kernels at the mean density.
+  auto level_of = [&](int64_t T) {
+    if (keys.lattice) return level_for(T);
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = 0; i < M; ++i)
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = std::min(lo[a], h.kgeo[4 * i + a]);
+        hi[a] = std::max(hi[a], h.kgeo[4 * i + a]);
+      }
+    double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]});
+    double vol = 1.0;
+    for (int a = 0; a < 3; ++a) vol *= std::max(hi[a] - lo[a], ext / 1024.0);
+    if (ext <= 0) return 0;
+    double edge = std::cbrt((double)T * vol / (double)M);
+    int l = (int)std::lround(std::log2(std::max(edge / keys.quantum, 1.0)));
+    return std::min(std::max(l, 0), 20);
+  };
+
+  // Forward: a wave holds one LDS trace segment of Lf samples for 64 sensors,
+  // so the tile size sets both the work per wave and the LDS per wave.  Tiles
+  // of 8 x 8 x 4 lattice nodes keep a segment near 12 KiB (measured best at
+  // the paper-scale shape); smaller tiles are used only when the problem is
+  // too small to give every CU several waves.
+  const int64_t nsg = (Nd + kWave - 1) / kWave;
+  int64_t Tf = g->fwd_tile;
+  if (Tf == 0) {
+    Tf = 256;
+    while (Tf > 64 && ((M + Tf - 1) / Tf) * nsg < 4096) Tf /= 2;
+  }
+  const int64_t Lcap = kMaxSegmentBytes / (kWave * 4);
+  for (;;) {
+    h.ftiles = make_tiles(skeys, h.kgeo, Tf, level_of(Tf));
+    p->Lf = segment_len(max_rho(h.ftiles), p->inv_vdt, p->hmax);
+    if (p->Lf <= Lcap || Tf <= 64) break;
+    Tf /= 2;
+  }
+  if (p->Lf > Lcap) return GPAIR_ERR_INVALID_ARG;
+  p->fwd_tile = (int32_t)Tf;
+  int W = g->fwd_waves ? g->fwd_waves : 4;
+  while (W > 1 && ((int64_t)W * p->Lf * kWave * 4 > kMaxSegmentBytes || W > nsg)) W /= 2;
+  p->fwd_waves = W;
+
+  int64_t Ta = g->adj_tile ? g->adj_tile : 256;
+  for (;;) {
+    h.atiles = make_tiles(skeys, h.kgeo, Ta, level_of(Ta));
+    p->La = segment_len(max_rho(h.atiles), p->inv_vdt, p->hmax);
+    if ((int64_t)p->La * kAdjSensorsPerStage * 4 <= kMaxSegmentBytes || Ta <= 64) break;
+    Ta /= 2;
+  }
+  if ((int64_t)p->La * kAdjSensorsPerStage * 4 > kMaxSegmentBytes) return GPAIR_ERR_INVALID_ARG;
+  p->adj_tile = (int32_t)Ta;
+  p->max_rho = std::max(max_rho(h.ftiles), max_rho(h.atiles));
+
+  // Far-field precondition: every kernel at least 10 sigma_max from every
+  // sensor.  Tile spheres give a lower bound; members are checked one by one
+  // only where that bound is below the limit.
+  const double near = 10.0 * g->sigma_max;
+  double lbmin = std::numeric_limits<double>::infinity();
+  for (size_t t = 0; t < h.ftiles.size(); ++t) {
+    const TileInfo &T = h.ftiles[t];
+    for (int32_t j = 0; j < Nd; ++j) {
+      double dx = h.sens[4 * j] - T.cx, dy = h.sens[4 * j + 1] - T.cy,
+             dz = h.sens[4 * j + 2] - T.cz;
+      double lb = std::sqrt(dx * dx + dy * dy + dz * dz) - T.rho;
+      lbmin = std::min(lbmin, lb);
+      if (lb >= near) continue;
+      for (int32_t i = T.start; i < T.start + T.count; ++i) {
+        double ex = h.sens[4 * j] - h.kgeo[4 * i], ey = h.sens[4 * j + 1] - h.kgeo[4 * i + 1],
+               ez = h.sens[4 * j + 2] - h.kgeo[4 * i + 2];
+        if (!(std::sqrt(ex * ex + ey * ey + ez * ez) >= near)) return GPAIR_ERR_NEAR_FIELD;
+      }
+    }
+  }
+  p->min_dist = std::max(lbmin, near);
+
+  p->lay = layout_for(M, Nd, h.ftiles.size(), h.atiles.size());
+  return GPAIR_OK;
+}
+
+}  // namespace gpair

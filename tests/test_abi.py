@@ -1,0 +1,121 @@
+"""The C-ABI library: exported symbols and host-side validation (CPU only;
+no call here launches GPU work)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from tests.conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "gpair.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gpair_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = header_functions()
+    for required in ("gpair_plan_create", "gpair_forward", "gpair_adjoint", "gpair_solve",
+                     "gpair_residual", "gpair_adam_update", "gpair_pgd_update"):
+        assert required in names
+
+
+def test_library_exports_every_header_function():
+    from paper_2602_03893_amd import _lib
+    missing = [n for n in header_functions() if not hasattr(_lib.lib, n)]
+    assert not missing, missing
+    assert _lib.gpair_abi_version() == 1
+
+
+def test_status_strings():
+    from paper_2602_03893_amd import _lib
+    for code, name in _lib.STATUS.items():
+        assert _lib.gpair_status_string(code).decode() == name
+    assert _lib.gpair_status_string(12345).decode() == "GPAIR_UNKNOWN_STATUS"
+
+
+def _geometry(centres, sensors, nt=256, dt=25e-9, c=1500.0, nsig=3.0, smax=0.1e-3,
+              fwd_tile=0, adj_tile=0, fwd_waves=0):
+    from paper_2602_03893_amd import _lib
+    fp = ctypes.POINTER(ctypes.c_float)
+    keep = [np.ascontiguousarray(np.asarray(centres, np.float32)[:, i]) for i in range(3)]
+    sens = np.ascontiguousarray(np.asarray(sensors, np.float32))
+    keep.append(sens)
+    g = _lib.Geometry()
+    g.n_kernels = len(centres)
+    g.cx, g.cy, g.cz = (k.ctypes.data_as(fp) for k in keep[:3])
+    g.n_sensors = sens.shape[0]
+    g.sensors = sens.ctypes.data_as(fp)
+    g.n_samples, g.dt, g.t0, g.c_sound = nt, dt, 0.0, c
+    g.n_sigma, g.sigma_max, g.fwd_tile, g.adj_tile = nsig, smax, fwd_tile, adj_tile
+    g.fwd_waves = fwd_waves
+    return g, keep
+
+
+def _create(g):
+    from paper_2602_03893_amd import _lib
+    h = ctypes.c_void_p()
+    st = _lib.gpair_plan_create(ctypes.byref(g), ctypes.byref(h))
+    return st, h
+
+
+def test_plan_creation_validates_arguments():
+    from paper_2602_03893_amd import _lib, inputs as I
+    cen = I.grid_centres(8, 8, 8, 0.1e-3)
+    sen = I.fibonacci_hemisphere(10, 10e-3)
+    g, keep = _geometry(cen, sen)
+    st, h = _create(g)
+    assert st == 0 and h.value
+    info = _lib.PlanInfo()
+    assert _lib.gpair_plan_get_info(h, ctypes.byref(info)) == 0
+    assert info.n_kernels == 512 and info.fwd_tiles >= 1 and info.max_taps == 17
+    assert sum(1 for _ in range(info.fwd_tiles)) == info.fwd_tiles
+    _lib.gpair_plan_destroy(h)
+    for field, bad, code in (("dt", 0.0, -1), ("c_sound", -1.0, -1), ("n_sigma", 0.0, -1),
+                             ("sigma_max", 0.0, -1), ("dt", float("nan"), -3),
+                             ("n_samples", 0, -1), ("fwd_tile", 100, -1),
+                             ("adj_tile", 32, -1), ("fwd_waves", 3, -1)):
+        g, keep = _geometry(cen, sen)
+        setattr(g, field, bad)
+        st, h = _create(g)
+        assert st == code, (field, st)
+        assert not h.value
+    st = _lib.gpair_plan_create(None, ctypes.byref(ctypes.c_void_p()))
+    assert st == -1
+
+
+def test_plan_rejects_nonfinite_geometry_and_near_field():
+    from paper_2602_03893_amd import inputs as I
+    cen = I.grid_centres(4, 4, 4, 0.1e-3)
+    sen = I.fibonacci_hemisphere(5, 10e-3)
+    bad = cen.copy()
+    bad[3, 1] = np.nan
+    g, keep = _geometry(bad, sen)
+    assert _create(g)[0] == -3
+    near = sen.copy()
+    near[2] = cen[5] + np.array([0.5e-3, 0, 0], np.float32)  # 0.5 mm < 10 sigma_max
+    g, keep = _geometry(cen, near)
+    assert _create(g)[0] == -2
+
+
+def test_point_cloud_tiles_cover_every_kernel_once():
+    """A random point cloud (not a lattice) is tiled; the tile table covers the
+    permuted kernel range exactly."""
+    from paper_2602_03893_amd import _lib
+    rng = np.random.default_rng(0)
+    cen = rng.uniform(-2e-3, 2e-3, (3000, 3)).astype(np.float32)
+    g, keep = _geometry(cen, np.array([[0, 0, -15e-3], [3e-3, 0, -14e-3]], np.float32),
+                        nt=1024)
+    st, h = _create(g)
+    assert st == 0
+    info = _lib.PlanInfo()
+    _lib.gpair_plan_get_info(h, ctypes.byref(info))
+    assert info.fwd_tiles >= 3000 // info.fwd_tile
+    assert info.adj_tiles >= 3000 // info.adj_tile
+    assert info.max_tile_radius < 4e-3
+    _lib.gpair_plan_destroy(h)

@@ -1,0 +1,202 @@
+"""GPU parity: the HIP operators (through the C ABI) against the float64 oracle.
+
+Bar (traces and gradients): relative L2 error <= 1e-5.  Window membership is
+decided in float64 on both sides; taps are float32 on the GPU.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ops as O
+from paper_2602_03893_amd import inputs as I
+from tests.conftest import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def make_case(centres, sensors, n_samples, sigma_max, dt=I.DT, t0=0.0, c=I.C_SOUND,
+              nsig=3.0, fwd_tile=0, adj_tile=0):
+    from paper_2602_03893_amd import Plan
+    plan = Plan(centres, sensors, n_samples, dt, c, n_sigma=nsig, sigma_max=sigma_max,
+                t0=t0, fwd_tile=fwd_tile, adj_tile=adj_tile)
+    g = O.Geometry(centres, sensors, n_samples, dt, t0, c, nsig)
+    return plan, g
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def workload_case(name, **kw):
+    w = I.WORKLOADS[name]
+    cen, sen = I.geometry_arrays(w)
+    plan, g = make_case(cen, sen, w.n_samples, w.smax, **kw)
+    return w, plan, g
+
+
+@pytest.fixture(scope="module")
+def toy():
+    _say("case: toy workload (16^3 kernels, 64 sensors, 512 samples)")
+    return workload_case("toy")
+
+
+def check_forward(plan, g, A, sigma, label):
+    _say(f"forward parity: {label}")
+    y = host(plan.forward(dev(A), dev(sigma)))
+    ref = O.forward(g, A.astype(np.float64), sigma.astype(np.float32).astype(np.float64))
+    err = rel_l2(y, ref)
+    _say(f"  rel L2 {err:.3e}")
+    assert err <= TOL, err
+    return y, ref
+
+
+def check_adjoint(plan, g, A, sigma, delta, label, want_sigma=True):
+    _say(f"adjoint parity: {label}")
+    gA, gS = plan.adjoint(dev(A), dev(sigma), dev(delta), want_sigma=want_sigma)
+    s64 = sigma.astype(np.float32).astype(np.float64)
+    rA, rS = O.adjoint(g, A.astype(np.float64), s64, delta.astype(np.float32).astype(np.float64),
+                       want_sigma=want_sigma)
+    eA = rel_l2(host(gA), rA)
+    _say(f"  gA rel L2 {eA:.3e}")
+    assert eA <= TOL, eA
+    if want_sigma:
+        eS = rel_l2(host(gS), rS)
+        _say(f"  gsigma rel L2 {eS:.3e}")
+        assert eS <= TOL, eS
+    return gA, gS
+
+
+def test_toy_forward_and_adjoint(toy):
+    w, plan, g = toy
+    A = I.phantom(w)
+    sigma = np.full(w.n_kernels, w.sigma, np.float32)
+    check_forward(plan, g, A, sigma, "toy")
+    delta = I.standard_normal((w.n_sensors, w.n_samples), seed=21)
+    check_adjoint(plan, g, A, sigma, delta, "toy")
+    check_adjoint(plan, g, A, sigma, delta, "toy, no sigma", want_sigma=False)
+
+
+def test_toy_per_kernel_sigma_and_signed_amplitudes(toy):
+    w, plan, g = toy
+    A = I.uniform(w.n_kernels, seed=3, lo=-1.0, hi=1.0)
+    sigma = I.uniform(w.n_kernels, seed=4, lo=0.2 * w.sigma, hi=w.sigma)
+    check_forward(plan, g, A, sigma, "toy, sigma_k ~ U[0.2, 1] sigma_max")
+    delta = I.standard_normal((w.n_sensors, w.n_samples), seed=22)
+    check_adjoint(plan, g, A, sigma, delta, "toy, per-kernel sigma")
+
+
+def test_adjointness_on_gpu(toy):
+    """<A x, y> = <x, A^T y> from GPU outputs (float64 inner products)."""
+    w, plan, g = toy
+    x = I.uniform(w.n_kernels, seed=5)
+    sigma = np.full(w.n_kernels, w.sigma, np.float32)
+    yv = I.standard_normal((w.n_sensors, w.n_samples), seed=6)
+    Ax = host(plan.forward(dev(x), dev(sigma)))
+    ATy, _ = plan.adjoint(dev(x), dev(sigma), dev(yv), want_sigma=False)
+    lhs = float(np.sum(Ax * yv.astype(np.float64)))
+    rhs = float(np.dot(x.astype(np.float64), host(ATy)))
+    assert abs(lhs - rhs) <= 1e-6 * abs(lhs)
+
+
+@pytest.mark.parametrize("fwd_tile,adj_tile", [(64, 64), (256, 128), (1024, 256)])
+def test_ragged_point_cloud_clipped_windows(fwd_tile, adj_tile):
+    """A random point cloud (not a lattice), N_d not a multiple of 64, tiles of
+    several sizes, and a time origin that cuts the earliest pulses at sample 0
+    and the latest at sample N_t - 1."""
+    _say(f"case: point cloud M=1000, N_d=70, tiles {fwd_tile}/{adj_tile}")
+    rng = np.random.default_rng(8)
+    cen = rng.uniform(-1.5e-3, 1.5e-3, (1000, 3)).astype(np.float32)
+    sen = I.fibonacci_hemisphere(70, 12e-3)
+    # pulses arrive between ~9.4 mm and ~14.6 mm: start the trace at 11 mm and
+    # stop it at 13 mm so both ends clip
+    t0 = 11e-3 / I.C_SOUND
+    nt = int((2e-3 / I.C_SOUND) / I.DT)
+    smax = 0.08e-3
+    plan, g = make_case(cen, sen, nt, smax, t0=t0, fwd_tile=fwd_tile, adj_tile=adj_tile)
+    A = I.uniform(1000, seed=9, lo=-0.5, hi=1.0)
+    sigma = I.uniform(1000, seed=10, lo=0.3 * smax, hi=smax)
+    y, ref = check_forward(plan, g, A, sigma, "point cloud")
+    assert np.abs(ref[:, 0]).max() > 0 and np.abs(ref[:, -1]).max() > 0
+    delta = I.standard_normal((70, nt), seed=11)
+    check_adjoint(plan, g, A, sigma, delta, "point cloud")
+
+
+def test_single_kernel_single_sensor():
+    _say("case: one kernel, one sensor")
+    cen = np.array([[0.3e-3, -0.2e-3, 0.1e-3]], np.float32)
+    sen = np.array([[0.0, 0.0, -10e-3]], np.float32)
+    plan, g = make_case(cen, sen, 400, 0.1e-3)
+    A = np.array([0.8], np.float32)
+    sigma = np.array([0.07e-3], np.float32)
+    check_forward(plan, g, A, sigma, "1x1")
+    check_adjoint(plan, g, A, sigma, I.standard_normal((1, 400), seed=1), "1x1")
+
+
+def test_sigma_violations_are_counted(toy):
+    w, plan, g = toy
+    before = plan.sigma_violations()
+    sigma = np.full(w.n_kernels, w.sigma, np.float32)
+    sigma[[3, 70, 900]] = [2 * w.sigma, -1.0, 0.0]
+    plan.forward(dev(np.ones(w.n_kernels, np.float32)), dev(sigma))
+    assert plan.sigma_violations() - before == 3
+
+
+def test_mid_workload_full(request):
+    _say("case: mid workload (64^3 kernels, 512 sensors, 2048 samples)")
+    w, plan, g = workload_case("mid")
+    A = I.phantom(w)
+    sigma = np.full(w.n_kernels, w.sigma, np.float32)
+    check_forward(plan, g, A, sigma, "mid")
+    delta = I.standard_normal((w.n_sensors, w.n_samples), seed=31)
+    check_adjoint(plan, g, A, sigma, delta, "mid")
+
+
+def test_paper_scale_sampled():
+    """8,388,608 kernels x 1024 sensors x 4096 samples: the forward on 16
+    sensors and the adjoint on 131,072 kernels (every 64th) against the
+    oracle, and the sigma-gradient against central differences of the oracle
+    loss <y, delta> at 64 random kernels."""
+    _say("case: paper workload (256x256x128 kernels, 1024 sensors, 4096 samples)")
+    w, plan, g = workload_case("paper")
+    A = I.phantom(w)
+    sigma = I.uniform(w.n_kernels, seed=12, lo=0.5 * w.smax, hi=w.smax)
+    y = host(plan.forward(dev(A), dev(sigma)))
+    rows = np.random.default_rng(13).choice(w.n_sensors, 16, replace=False)
+    ref = O.forward(g.subset_sensors(rows), A, sigma.astype(np.float64))
+    err = rel_l2(y[rows], ref)
+    _say(f"  forward (16 sensors) rel L2 {err:.3e}")
+    assert err <= TOL
+    delta = I.standard_normal((w.n_sensors, w.n_samples), seed=14)
+    gA, gS = plan.adjoint(dev(A), dev(sigma), dev(delta))
+    gA, gS = host(gA), host(gS)
+    ks = np.arange(0, w.n_kernels, 64)
+    rA, rS = O.adjoint(g.subset_kernels(ks), A[ks], sigma[ks].astype(np.float64),
+                       delta.astype(np.float64))
+    eA, eS = rel_l2(gA[ks], rA), rel_l2(gS[ks], rS)
+    _say(f"  adjoint (131072 kernels) gA {eA:.3e} gsigma {eS:.3e}")
+    assert eA <= TOL and eS <= TOL
+    # central differences of L(sigma_k) = <y(sigma), delta> at 64 kernels
+    pick = np.random.default_rng(15).choice(w.n_kernels, 64, replace=False)
+    d64 = delta.astype(np.float64)
+    fd = []
+    for k in pick:
+        gk = g.subset_kernels([k])
+        h = 1e-6 * float(sigma[k])
+        lp = np.sum(O.forward(gk, [A[k]], [float(sigma[k]) + h]) * d64)
+        lm = np.sum(O.forward(gk, [A[k]], [float(sigma[k]) - h]) * d64)
+        fd.append((lp - lm) / (2 * h))
+    fd = np.array(fd)
+    efd = np.abs(gS[pick] - fd) / np.maximum(np.abs(fd), 1e-3 * np.abs(fd).max())
+    _say(f"  gsigma vs central differences: max rel {efd.max():.3e}")
+    assert efd.max() <= 1e-3
