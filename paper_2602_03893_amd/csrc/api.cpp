@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "gpair_internal.h"
 
@@ -83,7 +84,19 @@ gpair_status gpair_plan_bind_workspace(gpair_plan p, void *workspace, size_t wor
     if (e == hipSuccess && n) e = hipMemcpyAsync(ws + off, src, n, hipMemcpyHostToDevice, s);
   };
   up(p->lay.sens, h.sens.data(), h.sens.size() * sizeof(double));
-  up(p->lay.kgeo, h.kgeo.data(), h.kgeo.size() * sizeof(double));
+  // Kernel records: centres now, coefficients on every operator call.
+  std::vector<KernelRec> rec;
+  try {
+    rec.assign((size_t)p->M, KernelRec{});
+  } catch (...) {
+    return GPAIR_ERR_INVALID_ARG;
+  }
+  for (int64_t i = 0; i < p->M; ++i) {
+    rec[i].cx = h.kgeo[4 * i];
+    rec[i].cy = h.kgeo[4 * i + 1];
+    rec[i].cz = h.kgeo[4 * i + 2];
+  }
+  up(p->lay.krec, rec.data(), rec.size() * sizeof(KernelRec));
   up(p->lay.perm, h.perm.data(), h.perm.size() * sizeof(int32_t));
   up(p->lay.ftiles, h.ftiles.data(), h.ftiles.size() * sizeof(TileInfo));
   up(p->lay.atiles, h.atiles.data(), h.atiles.size() * sizeof(TileInfo));

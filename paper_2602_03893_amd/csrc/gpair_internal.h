@@ -22,22 +22,27 @@ struct alignas(16) TileInfo {
 };
 static_assert(sizeof(TileInfo) == 48, "TileInfo layout");
 
-// Per-kernel coefficients, rebuilt on every operator call from (A, sigma).
+// One 64-byte record per kernel (permuted order), read by the forward as a
+// single scalar load.  The centre is written once when the plan is bound; the
+// coefficients are rebuilt on every operator call from (A, sigma).
 // With Delta = v*dt and c = -log2(e) / (2 sigma^2):
 //   exp(-d^2/(2 sigma^2)) = exp2(c d^2);
 //   the ratio of consecutive taps (d -> d - Delta) is q(d) = exp2(k2 + k1 d)
 //   with k1 = -2 c Delta, k2 = c Delta^2, and q itself is multiplied by
 //   rq = exp2(2 c Delta^2) from one tap to the next.
-struct alignas(32) KernelRec {
-  float amp;    // A_k
-  float c;      // -log2(e) / (2 sigma_k^2)
-  float k1;     // -2 c Delta
-  float k2;     // c Delta^2
-  float rq;     // exp2(2 c Delta^2)
-  int32_t ntap; // floor(2 h) + 1: most samples a window can hold
-  double h;     // n_sigma sigma_k / Delta: window half-width in samples
+struct alignas(64) KernelRec {
+  double cx, cy, cz;  // centre (m), float64 copy of the caller's float32
+  double h;           // n_sigma sigma_k / Delta: window half-width in samples
+  float amp;          // A_k
+  float c;            // -log2(e) / (2 sigma_k^2)
+  float k1;           // -2 c Delta
+  float k2;           // c Delta^2
+  float rq;           // exp2(2 c Delta^2)
+  int32_t ntap;       // floor(2 h) + 1: most samples a window can hold
+  double hlast;       // (ntap - 1) - h: tap ntap-1 is in the window iff the
+                      // first tap's offset nc - lo is >= hlast
 };
-static_assert(sizeof(KernelRec) == 32, "KernelRec layout");
+static_assert(sizeof(KernelRec) == 64, "KernelRec layout");
 
 constexpr int kWave = 64;
 constexpr int kAdjSensorsPerStage = 64; // sensors staged per LDS refill
@@ -47,7 +52,7 @@ constexpr int kXcds = 8;                // MI355X: 8 accelerator dies
 
 // Offsets (bytes) of each table inside the plan workspace.
 struct WorkspaceLayout {
-  size_t sens, kgeo, perm, ftiles, atiles, krec, counters, partials, total;
+  size_t sens, perm, ftiles, atiles, krec, counters, partials, total;
 };
 
 struct HostTables {
@@ -106,7 +111,6 @@ hipError_t launch_adam(int64_t n, float *x, const float *g, float *m, float *v,
 
 // Workspace pointers of a bound plan.
 inline double *ws_sens(const gpair_plan_s *p) { return (double *)(p->ws + p->lay.sens); }
-inline double *ws_kgeo(const gpair_plan_s *p) { return (double *)(p->ws + p->lay.kgeo); }
 inline int32_t *ws_perm(const gpair_plan_s *p) { return (int32_t *)(p->ws + p->lay.perm); }
 inline TileInfo *ws_ftiles(const gpair_plan_s *p) { return (TileInfo *)(p->ws + p->lay.ftiles); }
 inline TileInfo *ws_atiles(const gpair_plan_s *p) { return (TileInfo *)(p->ws + p->lay.atiles); }

@@ -64,15 +64,16 @@ __global__ __launch_bounds__(256) void prep_kernel(
     s = (s > smax_eff) ? smax_eff : ((s > 0.0) ? s : smax_eff);
   }
   const double c = -kLog2e / (2.0 * s * s);
-  KernelRec r;
+  const double h = nsig * s / vdt;
+  KernelRec &r = rec[i];  // the centre fields were written at plan binding
+  r.h = h;
   r.amp = a;
   r.c = (float)c;
   r.k1 = (float)(-2.0 * c * vdt);
   r.k2 = (float)(c * vdt * vdt);
   r.rq = (float)exp2(2.0 * c * vdt * vdt);
-  r.h = nsig * s / vdt;
-  r.ntap = (int32_t)floor(2.0 * r.h) + 1;
-  rec[i] = r;
+  r.ntap = (int32_t)floor(2.0 * h) + 1;
+  r.hlast = (double)(r.ntap - 1) - h;
 }
 
 // ---------------------------------------------------------------------------
@@ -108,11 +109,9 @@ __device__ __forceinline__ PairTerms pair_terms(double sx, double sy, double sz,
 // Forward.
 // ---------------------------------------------------------------------------
 struct FwdArgs {
-  const double4 *__restrict__ sens;
-  const double4 *__restrict__ kgeo;
-  const KernelRec *__restrict__ krec;
-  const TileInfo *__restrict__ tiles;
-  float *__restrict__ y;
+  const double4 *sens;
+  const TileInfo *tiles;
+  float *y;
   int64_t nlogical;
   int32_t Nd, Nt, nsg, nsgw, L;
   double inv_vdt, t0_over_dt, hmax, vdt;
@@ -149,8 +148,62 @@ __device__ __forceinline__ void taps_rmw(float *p, float f, float q, float d, fl
 // accumulate with plain read-modify-write: LDS float atomics are far slower
 // than plain accesses on this chip.  The waves of a workgroup walk the same
 // kernel records, which therefore stream once through the scalar cache.
+// Everything the tap loop of one kernel-sensor pair needs.
+struct Taps {
+  float f;       // w * exp(-d0^2 / (2 sigma^2)) with w = A / (2 r)
+  float q;       // ratio of the second tap's Gaussian factor to the first's
+  float d;       // d0 = r - v t of the first tap (m)
+  int o;         // first tap's slot in the lane's segment
+  bool last_ok;  // tap ntap-1 is inside the window
+};
+
+__device__ __forceinline__ Taps pair_taps(const double4 &s, const KernelRec &r, int nb, int L,
+                                          double inv_vdt, double t0_over_dt, double vdt) {
+  const PairTerms pt = pair_terms(s.x, s.y, s.z, r.cx, r.cy, r.cz, r.h, inv_vdt, t0_over_dt);
+  Taps t;
+  t.d = (float)(pt.fr * vdt);
+  t.last_ok = pt.fr >= r.hlast;
+  // By construction of nb and L every tap slot o + i (i < ntap) is at most
+  // L - 2; the clamp only keeps LDS accesses in range if that were violated.
+  t.o = min(max(pt.lo - nb, 0), L - 1 - r.ntap);
+  t.f = (0.5f * r.amp) * pt.rinv * __builtin_amdgcn_exp2f(r.c * t.d * t.d);
+  t.q = __builtin_amdgcn_exp2f(fmaf(r.k1, t.d, r.k2));
+  return t;
+}
+
+// ntap is wave-uniform: dispatch to a fully unrolled read-modify-write of
+// ceil(ntap/2) sample pairs.
+__device__ __forceinline__ void add_taps(float *p, const Taps &t, const KernelRec &r,
+                                         float vdt_f) {
+  float f = t.f, q = t.q, d = t.d;
+  switch ((r.ntap + 1) >> 1) {
+    case 1: taps_rmw<1>(p, f, q, d, r.rq, vdt_f, r.ntap, t.last_ok); break;
+    case 2: taps_rmw<2>(p, f, q, d, r.rq, vdt_f, r.ntap, t.last_ok); break;
+    case 3: taps_rmw<3>(p, f, q, d, r.rq, vdt_f, r.ntap, t.last_ok); break;
+    case 4: taps_rmw<4>(p, f, q, d, r.rq, vdt_f, r.ntap, t.last_ok); break;
+    case 5: taps_rmw<5>(p, f, q, d, r.rq, vdt_f, r.ntap, t.last_ok); break;
+    case 6: taps_rmw<6>(p, f, q, d, r.rq, vdt_f, r.ntap, t.last_ok); break;
+    case 7: taps_rmw<7>(p, f, q, d, r.rq, vdt_f, r.ntap, t.last_ok); break;
+    case 8: taps_rmw<8>(p, f, q, d, r.rq, vdt_f, r.ntap, t.last_ok); break;
+    case 9: taps_rmw<9>(p, f, q, d, r.rq, vdt_f, r.ntap, t.last_ok); break;
+    default: {
+      const int nfull = r.ntap - 1;
+      for (int i = 0; i < nfull; ++i) {
+        p[i * kWave] += f * d;
+        d -= vdt_f;
+        f *= q;
+        q *= r.rq;
+      }
+      p[nfull * kWave] += t.last_ok ? f * d : 0.0f;
+    }
+  }
+}
+
+// The record array is a direct kernel argument (const, restrict) so that its
+// uniform loads stay scalar loads next to the LDS stores of the tap loop.
 template <int WAVES>
-__global__ __launch_bounds__(WAVES * kWave) void forward_kernel(FwdArgs a) {
+__global__ __launch_bounds__(WAVES * kWave) void forward_kernel(
+    const KernelRec *__restrict__ krec, FwdArgs a) {
   extern __shared__ float seg_all[];  // [WAVES][L][64]
 
   const int64_t logical = xcd_logical_block(a.nlogical);
@@ -174,56 +227,29 @@ __global__ __launch_bounds__(WAVES * kWave) void forward_kernel(FwdArgs a) {
     nb = (int)floor((R - T.rho) * a.inv_vdt - a.t0_over_dt - a.hmax) - 1;
   }
 
-  if (wave_live) {
-    for (int i = 0; i < a.L; ++i) col[i * kWave] = 0.0f;
+  if (!wave_live) return;  // the last workgroup may have fewer sensor groups
+  for (int i = 0; i < a.L; ++i) col[i * kWave] = 0.0f;
+  {
     const float vdt_f = (float)a.vdt;
     const int kend = T.start + T.count;
+    KernelRec next = krec[T.start];
     for (int k = T.start; k < kend; ++k) {
-      const double4 c = a.kgeo[k];
-      const KernelRec r = a.krec[k];
-      const PairTerms pt = pair_terms(s.x, s.y, s.z, c.x, c.y, c.z, r.h, a.inv_vdt,
-                                      a.t0_over_dt);
-      const float d0 = (float)(pt.fr * a.vdt);
-      const bool last_ok = (pt.fr + r.h) >= (double)(r.ntap - 1);
-      // Offset of the first tap in the segment.  By construction of nb and L
-      // every tap index o + i (i < ntap) is at most L - 2; the clamp only
-      // keeps LDS accesses in range if that were ever violated.
-      int o = pt.lo - nb;
-      o = min(max(o, 0), a.L - 1 - r.ntap);
-      float f = (0.5f * r.amp) * pt.rinv * __builtin_amdgcn_exp2f(r.c * d0 * d0);
-      float q = __builtin_amdgcn_exp2f(fmaf(r.k1, d0, r.k2));
-      float d = d0;
-      float *p = col + o * kWave;
-      // ntap is wave-uniform: dispatch to a fully unrolled read-modify-write
-      // of ceil(ntap/2) sample pairs.
-      switch ((r.ntap + 1) >> 1) {
-        case 1: taps_rmw<1>(p, f, q, d, r.rq, vdt_f, r.ntap, last_ok); break;
-        case 2: taps_rmw<2>(p, f, q, d, r.rq, vdt_f, r.ntap, last_ok); break;
-        case 3: taps_rmw<3>(p, f, q, d, r.rq, vdt_f, r.ntap, last_ok); break;
-        case 4: taps_rmw<4>(p, f, q, d, r.rq, vdt_f, r.ntap, last_ok); break;
-        case 5: taps_rmw<5>(p, f, q, d, r.rq, vdt_f, r.ntap, last_ok); break;
-        case 6: taps_rmw<6>(p, f, q, d, r.rq, vdt_f, r.ntap, last_ok); break;
-        case 7: taps_rmw<7>(p, f, q, d, r.rq, vdt_f, r.ntap, last_ok); break;
-        case 8: taps_rmw<8>(p, f, q, d, r.rq, vdt_f, r.ntap, last_ok); break;
-        case 9: taps_rmw<9>(p, f, q, d, r.rq, vdt_f, r.ntap, last_ok); break;
-        default: {
-          const int nfull = r.ntap - 1;
-          for (int i = 0; i < nfull; ++i) {
-            p[i * kWave] += f * d;
-            d -= vdt_f;
-            f *= q;
-            q *= r.rq;
-          }
-          p[nfull * kWave] += last_ok ? f * d : 0.0f;
-        }
-      }
+      const KernelRec r = next;
+      if (k + 1 < kend) next = krec[k + 1];  // prefetch one record ahead
+      const Taps t = pair_taps(s, r, nb, a.L, a.inv_vdt, a.t0_over_dt, a.vdt);
+      add_taps(col + t.o * kWave, t, r, vdt_f);
     }
   }
-  __syncthreads();
-  if (!wave_live) return;
+  // The segment is private to this wave and a wave's LDS operations complete
+  // in issue order, so the flush below (which reads other lanes' columns)
+  // needs no workgroup barrier; this only keeps the compiler from moving
+  // memory operations across.
+  __builtin_amdgcn_wave_barrier();
 
   // Flush the wave's 64 rows: lanes walk the samples of one row so that
-  // consecutive lanes add to consecutive addresses of y.
+  // consecutive lanes add to consecutive addresses of y (coalesced float
+  // atomics; per-lane rows would scatter one atomic per cache line, which
+  // measured twice as slow with dense amplitudes).
   for (int row = 0; row < kWave; ++row) {
     const int jr = sg * kWave + row;
     if (jr >= a.Nd) break;
@@ -241,14 +267,12 @@ __global__ __launch_bounds__(WAVES * kWave) void forward_kernel(FwdArgs a) {
 // Adjoint.
 // ---------------------------------------------------------------------------
 struct AdjArgs {
-  const double4 *__restrict__ sens;
-  const double4 *__restrict__ kgeo;
-  const KernelRec *__restrict__ krec;
-  const TileInfo *__restrict__ tiles;
-  const int32_t *__restrict__ perm;
-  const float *__restrict__ delta;
-  float *__restrict__ gA;
-  float *__restrict__ gS;
+  const KernelRec *krec;
+  const TileInfo *tiles;
+  const int32_t *perm;
+  const float *delta;
+  float *gA;
+  float *gS;
   int64_t nlogical;
   int32_t Nd, Nt, L, ntap_max;
   double inv_vdt, t0_over_dt, hmax, vdt, nsig;
@@ -264,7 +288,8 @@ __device__ __forceinline__ int wave_max(int x) {
 }
 
 template <int BLOCK, bool SIG>
-__global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjArgs a) {
+__global__ __launch_bounds__(BLOCK) void adjoint_kernel(const double4 *__restrict__ sens,
+                                                       AdjArgs a) {
   extern __shared__ float stage[];  // [kAdjSensorsPerStage][L]
   __shared__ int nbs[kAdjSensorsPerStage];
 
@@ -274,7 +299,6 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjArgs a) {
   const int t = threadIdx.x;
   const bool live = t < T.count;
   const int64_t i = T.start + (live ? t : 0);
-  const double4 c = a.kgeo[i];
   const KernelRec r = a.krec[i];
 
   // Taps every lane of the wave has (uniform loop) and the most any has.
@@ -291,7 +315,7 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjArgs a) {
     const int nsb = min(kAdjSensorsPerStage, a.Nd - j0);
     __syncthreads();
     if (t < nsb) {
-      const double4 s = a.sens[j0 + t];
+      const double4 s = sens[j0 + t];
       const double dx = s.x - T.cx, dy = s.y - T.cy, dz = s.z - T.cz;
       const double R = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
       nbs[t] = (int)floor((R - T.rho) * a.inv_vdt - a.t0_over_dt - a.hmax) - 1;
@@ -306,12 +330,12 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(AdjArgs a) {
 
     float pA = 0.0f, pS = 0.0f;
     for (int js = 0; js < nsb; ++js) {
-      const double4 s = a.sens[j0 + js];
+      const double4 s = sens[j0 + js];
       const int nb = nbs[js];
-      const PairTerms pt = pair_terms(s.x, s.y, s.z, c.x, c.y, c.z, r.h, a.inv_vdt,
+      const PairTerms pt = pair_terms(s.x, s.y, s.z, r.cx, r.cy, r.cz, r.h, a.inv_vdt,
                                       a.t0_over_dt);
       const float d0 = (float)(pt.fr * a.vdt);
-      const int nvalid = ((pt.fr + r.h) >= (double)(r.ntap - 1)) ? r.ntap : r.ntap - 1;
+      const int nvalid = (pt.fr >= r.hlast) ? r.ntap : r.ntap - 1;
       int o = pt.lo - nb;
       o = min(max(o, 0), omax);
       float f = 0.5f * pt.rinv * __builtin_amdgcn_exp2f(r.c * d0 * d0);
@@ -367,8 +391,6 @@ hipError_t launch_prep(const gpair_plan_s *p, const float *A, const float *sigma
 hipError_t launch_forward(const gpair_plan_s *p, float *y, hipStream_t s) {
   FwdArgs a;
   a.sens = (const double4 *)ws_sens(p);
-  a.kgeo = (const double4 *)ws_kgeo(p);
-  a.krec = ws_krec(p);
   a.tiles = ws_ftiles(p);
   a.y = y;
   a.Nd = p->Nd;
@@ -385,9 +407,9 @@ hipError_t launch_forward(const gpair_plan_s *p, float *y, hipStream_t s) {
   const size_t lds = (size_t)W * p->Lf * kWave * sizeof(float);
   const unsigned int grid = xcd_grid(a.nlogical);
   switch (W) {
-    case 1: forward_kernel<1><<<grid, kWave, lds, s>>>(a); break;
-    case 2: forward_kernel<2><<<grid, 2 * kWave, lds, s>>>(a); break;
-    default: forward_kernel<4><<<grid, 4 * kWave, lds, s>>>(a); break;
+    case 1: forward_kernel<1><<<grid, kWave, lds, s>>>(ws_krec(p), a); break;
+    case 2: forward_kernel<2><<<grid, 2 * kWave, lds, s>>>(ws_krec(p), a); break;
+    default: forward_kernel<4><<<grid, 4 * kWave, lds, s>>>(ws_krec(p), a); break;
   }
   return hipGetLastError();
 }
@@ -395,8 +417,6 @@ hipError_t launch_forward(const gpair_plan_s *p, float *y, hipStream_t s) {
 hipError_t launch_adjoint(const gpair_plan_s *p, const float *delta, float *gA,
                           float *gsigma, hipStream_t s) {
   AdjArgs a;
-  a.sens = (const double4 *)ws_sens(p);
-  a.kgeo = (const double4 *)ws_kgeo(p);
   a.krec = ws_krec(p);
   a.tiles = ws_atiles(p);
   a.perm = ws_perm(p);
@@ -418,16 +438,16 @@ hipError_t launch_adjoint(const gpair_plan_s *p, const float *delta, float *gA,
   const bool sig = gsigma != nullptr;
   switch (p->adj_tile) {
     case 64:
-      if (sig) adjoint_kernel<64, true><<<grid, 64, lds, s>>>(a);
-      else adjoint_kernel<64, false><<<grid, 64, lds, s>>>(a);
+      if (sig) adjoint_kernel<64, true><<<grid, 64, lds, s>>>((const double4 *)ws_sens(p), a);
+      else adjoint_kernel<64, false><<<grid, 64, lds, s>>>((const double4 *)ws_sens(p), a);
       break;
     case 128:
-      if (sig) adjoint_kernel<128, true><<<grid, 128, lds, s>>>(a);
-      else adjoint_kernel<128, false><<<grid, 128, lds, s>>>(a);
+      if (sig) adjoint_kernel<128, true><<<grid, 128, lds, s>>>((const double4 *)ws_sens(p), a);
+      else adjoint_kernel<128, false><<<grid, 128, lds, s>>>((const double4 *)ws_sens(p), a);
       break;
     default:
-      if (sig) adjoint_kernel<256, true><<<grid, 256, lds, s>>>(a);
-      else adjoint_kernel<256, false><<<grid, 256, lds, s>>>(a);
+      if (sig) adjoint_kernel<256, true><<<grid, 256, lds, s>>>((const double4 *)ws_sens(p), a);
+      else adjoint_kernel<256, false><<<grid, 256, lds, s>>>((const double4 *)ws_sens(p), a);
       break;
   }
   return hipGetLastError();

@@ -166,7 +166,6 @@ WorkspaceLayout layout_for(int64_t M, int32_t Nd, size_t nft, size_t nat) {
   WorkspaceLayout l{};
   size_t off = 0;
   l.sens = off;     off = align256(off + (size_t)Nd * 32);
-  l.kgeo = off;     off = align256(off + (size_t)M * 32);
   l.perm = off;     off = align256(off + (size_t)M * 4);
   l.ftiles = off;   off = align256(off + nft * sizeof(TileInfo));
   l.atiles = off;   off = align256(off + nat * sizeof(TileInfo));
