@@ -117,14 +117,15 @@ struct FwdArgs {
   double inv_vdt, t0_over_dt, hmax, vdt;
 };
 
-// Add the taps of one pair into a lane's segment column: 2P samples from p
-// (stride 64 floats).  Taps 0 .. ntap-2 are in the window for every lane,
-// tap ntap-1 only where last_ok, and a tap ntap (when 2P = ntap + 1) is
-// padding.  ntap is 2P - 1 or 2P.  All reads are issued before the
-// arithmetic so their latency overlaps it.
+// Add the taps of one kernel-sensor pair into the lane's segment column p
+// (stride 64 floats): 2P samples, of which the first nvalid are inside the
+// window (nvalid = ntap - 1 or ntap, and ntap >= 2P - 2, so only the last
+// three can be outside).  All reads are issued before the arithmetic so their
+// latency overlaps it; reads and writes pair up (one paired LDS access per
+// two samples).
 template <int P>
 __device__ __forceinline__ void taps_rmw(float *p, float f, float q, float d, float rq,
-                                         float vdt, int ntap, bool last_ok) {
+                                         float vdt, int nvalid) {
   float old[2 * P];
 #pragma unroll
   for (int i = 0; i < 2 * P; ++i) old[i] = p[i * kWave];
@@ -136,18 +137,13 @@ __device__ __forceinline__ void taps_rmw(float *p, float f, float q, float d, fl
     f *= q;
     q *= rq;
   }
-  const bool even = ntap == 2 * P;
-  if (!(even || last_ok)) t[2 * P - 2] = 0.0f;
-  if (!(even && last_ok)) t[2 * P - 1] = 0.0f;
+#pragma unroll
+  for (int i = (2 * P - 3 > 0 ? 2 * P - 3 : 0); i < 2 * P; ++i)
+    if (i >= nvalid) t[i] = 0.0f;
 #pragma unroll
   for (int i = 0; i < 2 * P; ++i) p[i * kWave] = old[i] + t[i];
 }
 
-// One workgroup = one tile x WAVES sensor groups of 64.  Every wave owns a
-// private LDS segment [L][64] (sample-major, one column per sensor), so taps
-// accumulate with plain read-modify-write: LDS float atomics are far slower
-// than plain accesses on this chip.  The waves of a workgroup walk the same
-// kernel records, which therefore stream once through the scalar cache.
 // Everything the tap loop of one kernel-sensor pair needs.
 struct Taps {
   float f;       // w * exp(-d0^2 / (2 sigma^2)) with w = A / (2 r)
@@ -157,44 +153,62 @@ struct Taps {
   bool last_ok;  // tap ntap-1 is inside the window
 };
 
-__device__ __forceinline__ Taps pair_taps(const double4 &s, const KernelRec &r, int nb, int L,
+__device__ __forceinline__ Taps pair_taps(const double4 &s, const KernelRec &r, int nb, int omax,
                                           double inv_vdt, double t0_over_dt, double vdt) {
   const PairTerms pt = pair_terms(s.x, s.y, s.z, r.cx, r.cy, r.cz, r.h, inv_vdt, t0_over_dt);
   Taps t;
   t.d = (float)(pt.fr * vdt);
   t.last_ok = pt.fr >= r.hlast;
   // By construction of nb and L every tap slot o + i (i < ntap) is at most
-  // L - 2; the clamp only keeps LDS accesses in range if that were violated.
-  t.o = min(max(pt.lo - nb, 0), L - 1 - r.ntap);
+  // L - 4; the clamp (omax = L - 1 - the samples the caller writes) only keeps
+  // LDS accesses in range if that were ever violated.
+  t.o = min(max(pt.lo - nb, 0), omax);
   t.f = (0.5f * r.amp) * pt.rinv * __builtin_amdgcn_exp2f(r.c * t.d * t.d);
   t.q = __builtin_amdgcn_exp2f(fmaf(r.k1, t.d, r.k2));
   return t;
 }
 
-// ntap is wave-uniform: dispatch to a fully unrolled read-modify-write of
-// ceil(ntap/2) sample pairs.
-__device__ __forceinline__ void add_taps(float *p, const Taps &t, const KernelRec &r,
-                                         float vdt_f) {
+// Taps of one pair with any tap count (the general path).
+__device__ __forceinline__ void add_taps_any(float *p, const Taps &t, const KernelRec &r,
+                                             float vdt_f) {
   float f = t.f, q = t.q, d = t.d;
-  switch ((r.ntap + 1) >> 1) {
-    case 1: taps_rmw<1>(p, f, q, d, r.rq, vdt_f, r.ntap, t.last_ok); break;
-    case 2: taps_rmw<2>(p, f, q, d, r.rq, vdt_f, r.ntap, t.last_ok); break;
-    case 3: taps_rmw<3>(p, f, q, d, r.rq, vdt_f, r.ntap, t.last_ok); break;
-    case 4: taps_rmw<4>(p, f, q, d, r.rq, vdt_f, r.ntap, t.last_ok); break;
-    case 5: taps_rmw<5>(p, f, q, d, r.rq, vdt_f, r.ntap, t.last_ok); break;
-    case 6: taps_rmw<6>(p, f, q, d, r.rq, vdt_f, r.ntap, t.last_ok); break;
-    case 7: taps_rmw<7>(p, f, q, d, r.rq, vdt_f, r.ntap, t.last_ok); break;
-    case 8: taps_rmw<8>(p, f, q, d, r.rq, vdt_f, r.ntap, t.last_ok); break;
-    case 9: taps_rmw<9>(p, f, q, d, r.rq, vdt_f, r.ntap, t.last_ok); break;
-    default: {
-      const int nfull = r.ntap - 1;
-      for (int i = 0; i < nfull; ++i) {
-        p[i * kWave] += f * d;
-        d -= vdt_f;
-        f *= q;
-        q *= r.rq;
-      }
-      p[nfull * kWave] += t.last_ok ? f * d : 0.0f;
+  const int nfull = r.ntap - 1;
+  for (int i = 0; i < nfull; ++i) {
+    p[i * kWave] += f * d;
+    d -= vdt_f;
+    f *= q;
+    q *= r.rq;
+  }
+  p[nfull * kWave] += t.last_ok ? f * d : 0.0f;
+}
+
+struct FwdLoop {
+  const KernelRec *krec;
+  double4 s;
+  int nb, L, omax;
+  double inv_vdt, t0_over_dt, vdt;
+  float vdt_f;
+};
+
+// The kernel loop of one wave over its tile when every kernel of the tile
+// has 2P - 2 .. 2P taps.  Two records are in flight in alternating scalar
+// registers (no copies), and the tap count needs no per-kernel dispatch.
+template <int P>
+__device__ __forceinline__ void kernel_loop(const FwdLoop &c, float *col, int k0, int kend) {
+  KernelRec ra = c.krec[k0], rb;
+  for (int k = k0; k < kend; k += 2) {
+    if (k + 1 < kend) rb = c.krec[k + 1];
+    {
+      const Taps t = pair_taps(c.s, ra, c.nb, c.omax, c.inv_vdt, c.t0_over_dt, c.vdt);
+      taps_rmw<P>(col + t.o * kWave, t.f, t.q, t.d, ra.rq, c.vdt_f,
+                  ra.ntap - (t.last_ok ? 0 : 1));
+    }
+    if (k + 1 >= kend) break;
+    if (k + 2 < kend) ra = c.krec[k + 2];
+    {
+      const Taps t = pair_taps(c.s, rb, c.nb, c.omax, c.inv_vdt, c.t0_over_dt, c.vdt);
+      taps_rmw<P>(col + t.o * kWave, t.f, t.q, t.d, rb.rq, c.vdt_f,
+                  rb.ntap - (t.last_ok ? 0 : 1));
     }
   }
 }
@@ -229,15 +243,51 @@ __global__ __launch_bounds__(WAVES * kWave) void forward_kernel(
 
   if (!wave_live) return;  // the last workgroup may have fewer sensor groups
   for (int i = 0; i < a.L; ++i) col[i * kWave] = 0.0f;
-  {
-    const float vdt_f = (float)a.vdt;
-    const int kend = T.start + T.count;
-    KernelRec next = krec[T.start];
+
+  // Tap-count range of the tile (kernels' ntap), read once per wave.
+  int nmin = 1 << 30, nmax = 0;
+  for (int i = T.start + lane; i < T.start + T.count; i += kWave) {
+    const int n = krec[i].ntap;
+    nmin = min(nmin, n);
+    nmax = max(nmax, n);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    nmin = min(nmin, __shfl_xor(nmin, off, kWave));
+    nmax = max(nmax, __shfl_xor(nmax, off, kWave));
+  }
+  nmin = __builtin_amdgcn_readfirstlane(nmin);
+  nmax = __builtin_amdgcn_readfirstlane(nmax);
+  const int P = (nmax + 1) >> 1;
+
+  FwdLoop c;
+  c.krec = krec;
+  c.s = s;
+  c.nb = nb;
+  c.L = a.L;
+  c.inv_vdt = a.inv_vdt;
+  c.t0_over_dt = a.t0_over_dt;
+  c.vdt = a.vdt;
+  c.vdt_f = (float)a.vdt;
+  const int kend = T.start + T.count;
+  if (nmin >= 2 * P - 2 && P <= 9) {
+    c.omax = a.L - 1 - 2 * P;
+    switch (P) {
+      case 1: kernel_loop<1>(c, col, T.start, kend); break;
+      case 2: kernel_loop<2>(c, col, T.start, kend); break;
+      case 3: kernel_loop<3>(c, col, T.start, kend); break;
+      case 4: kernel_loop<4>(c, col, T.start, kend); break;
+      case 5: kernel_loop<5>(c, col, T.start, kend); break;
+      case 6: kernel_loop<6>(c, col, T.start, kend); break;
+      case 7: kernel_loop<7>(c, col, T.start, kend); break;
+      case 8: kernel_loop<8>(c, col, T.start, kend); break;
+      default: kernel_loop<9>(c, col, T.start, kend); break;
+    }
+  } else {
+    // Widely varying widths inside one tile: per-kernel tap loop.
     for (int k = T.start; k < kend; ++k) {
-      const KernelRec r = next;
-      if (k + 1 < kend) next = krec[k + 1];  // prefetch one record ahead
-      const Taps t = pair_taps(s, r, nb, a.L, a.inv_vdt, a.t0_over_dt, a.vdt);
-      add_taps(col + t.o * kWave, t, r, vdt_f);
+      const KernelRec r = krec[k];
+      const Taps t = pair_taps(s, r, nb, a.L - 1 - r.ntap, a.inv_vdt, a.t0_over_dt, a.vdt);
+      add_taps_any(col + t.o * kWave, t, r, c.vdt_f);
     }
   }
   // The segment is private to this wave and a wave's LDS operations complete

@@ -153,8 +153,11 @@ double max_rho(const std::vector<TileInfo> &t) {
   return r;
 }
 
+// Samples of a (tile, sensor) trace segment: the tile's time shell widened
+// by the window on both sides, plus slack for rounding and for the padding
+// taps the unrolled forward writes past a window's end.
 int segment_len(double rho, double inv_vdt, double hmax) {
-  double L = std::ceil(2.0 * rho * inv_vdt + 2.0 * hmax) + 5.0;
+  double L = std::ceil(2.0 * rho * inv_vdt + 2.0 * hmax) + 7.0;
   return L > 1e9 ? 1000000000 : (int)L;
 }
 

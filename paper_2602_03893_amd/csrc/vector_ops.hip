@@ -47,11 +47,11 @@ __global__ __launch_bounds__(kVecBlock) void residual_partial_kernel(
   double s_rr = 0.0, s_bb = 0.0;
   const int64_t stride = (int64_t)gridDim.x * kVecBlock;
   for (int64_t i = (int64_t)blockIdx.x * kVecBlock + threadIdx.x; i < n; i += stride) {
-    const float bi = b[i];
-    const float ri = y[i] - bi;
-    s_rr += (double)ri * (double)ri;
+    const float yi = y[i], bi = b[i];
+    const double rd = (double)yi - (double)bi;  // exact difference for the norm
+    s_rr += rd * rd;
     s_bb += (double)bi * (double)bi;
-    if (delta) delta[i] = scale * ri;
+    if (delta) delta[i] = scale * (yi - bi);
   }
   block_sum2(s_rr, s_bb, sh);
   if (threadIdx.x == 0) {
