@@ -28,6 +28,21 @@ FLOP_TAP_FWD = 7      # d, d^2, scale, exp, * d, * A/(2r), accumulate
 FLOP_TAP_ADJ = 10     # d, d^2, scale, exp, * d, * delta, acc A, * d^2, acc sigma, (d^3 reuse)
 FLOP_PAIR = 25        # distance (3 sub, 3 fma, sqrt), window bounds, 1/(2r), tap setup
 
+# HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (dense amplitudes,
+# scaled by the counts a 256 MiB device copy gives: fetch x2.0, write x1.0), keyed
+# by the sha256 prefix of the kernel source they were measured on; when the source
+# differs, the figure no longer applies and `traffic` is null.
+MEASURED_TRAFFIC = {
+    "e030a14f1607367e": {"forward_kernel": 5.396e9, "adjoint_kernel": 0.697e9},
+}
+
+
+def kernel_source_hash():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2602_03893_amd", "csrc", "operators.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -187,7 +202,8 @@ def main():
         "plan_s": t_plan,
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None},
+                     "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": MEASURED_TRAFFIC.get(kernel_source_hash(), {}).get(dom)},
     }
     if not args.no_cpu_baseline:
         log("bench: timing the float64 oracle on a sample (cpu_baseline)")
