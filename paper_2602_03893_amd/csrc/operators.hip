@@ -118,30 +118,30 @@ struct FwdArgs {
 };
 
 // Add the taps of one kernel-sensor pair into the lane's segment column p
-// (stride 64 floats): 2P samples, of which the first nvalid are inside the
-// window (nvalid = ntap - 1 or ntap, and ntap >= 2P - 2, so only the last
+// (stride 64 floats): NT samples, of which the first nvalid are inside the
+// window (nvalid = ntap - 1 or ntap, and ntap >= NT - 2, so only the last
 // three can be outside).  All reads are issued before the arithmetic so their
-// latency overlaps it; reads and writes pair up (one paired LDS access per
-// two samples).
-template <int P>
+// latency overlaps it; consecutive reads and writes pair up (one paired LDS
+// access per two samples).
+template <int NT>
 __device__ __forceinline__ void taps_rmw(float *p, float f, float q, float d, float rq,
                                          float vdt, int nvalid) {
-  float old[2 * P];
+  float old[NT];
 #pragma unroll
-  for (int i = 0; i < 2 * P; ++i) old[i] = p[i * kWave];
-  float t[2 * P];
+  for (int i = 0; i < NT; ++i) old[i] = p[i * kWave];
+  float t[NT];
 #pragma unroll
-  for (int i = 0; i < 2 * P; ++i) {
+  for (int i = 0; i < NT; ++i) {
     t[i] = f * d;
     d -= vdt;
     f *= q;
     q *= rq;
   }
 #pragma unroll
-  for (int i = (2 * P - 3 > 0 ? 2 * P - 3 : 0); i < 2 * P; ++i)
+  for (int i = (NT - 3 > 0 ? NT - 3 : 0); i < NT; ++i)
     if (i >= nvalid) t[i] = 0.0f;
 #pragma unroll
-  for (int i = 0; i < 2 * P; ++i) p[i * kWave] = old[i] + t[i];
+  for (int i = 0; i < NT; ++i) p[i * kWave] = old[i] + t[i];
 }
 
 // Everything the tap loop of one kernel-sensor pair needs.
@@ -191,24 +191,24 @@ struct FwdLoop {
 };
 
 // The kernel loop of one wave over its tile when every kernel of the tile
-// has 2P - 2 .. 2P taps.  Two records are in flight in alternating scalar
-// registers (no copies), and the tap count needs no per-kernel dispatch.
-template <int P>
+// has NT - 2 .. NT taps.  Two records are in flight in alternating registers
+// (no copies), and the tap count needs no per-kernel dispatch.
+template <int NT>
 __device__ __forceinline__ void kernel_loop(const FwdLoop &c, float *col, int k0, int kend) {
   KernelRec ra = c.krec[k0], rb;
   for (int k = k0; k < kend; k += 2) {
     if (k + 1 < kend) rb = c.krec[k + 1];
     {
       const Taps t = pair_taps(c.s, ra, c.nb, c.omax, c.inv_vdt, c.t0_over_dt, c.vdt);
-      taps_rmw<P>(col + t.o * kWave, t.f, t.q, t.d, ra.rq, c.vdt_f,
-                  ra.ntap - (t.last_ok ? 0 : 1));
+      taps_rmw<NT>(col + t.o * kWave, t.f, t.q, t.d, ra.rq, c.vdt_f,
+                   ra.ntap - (t.last_ok ? 0 : 1));
     }
     if (k + 1 >= kend) break;
     if (k + 2 < kend) ra = c.krec[k + 2];
     {
       const Taps t = pair_taps(c.s, rb, c.nb, c.omax, c.inv_vdt, c.t0_over_dt, c.vdt);
-      taps_rmw<P>(col + t.o * kWave, t.f, t.q, t.d, rb.rq, c.vdt_f,
-                  rb.ntap - (t.last_ok ? 0 : 1));
+      taps_rmw<NT>(col + t.o * kWave, t.f, t.q, t.d, rb.rq, c.vdt_f,
+                   rb.ntap - (t.last_ok ? 0 : 1));
     }
   }
 }
@@ -257,8 +257,6 @@ __global__ __launch_bounds__(WAVES * kWave) void forward_kernel(
   }
   nmin = __builtin_amdgcn_readfirstlane(nmin);
   nmax = __builtin_amdgcn_readfirstlane(nmax);
-  const int P = (nmax + 1) >> 1;
-
   FwdLoop c;
   c.krec = krec;
   c.s = s;
@@ -269,18 +267,17 @@ __global__ __launch_bounds__(WAVES * kWave) void forward_kernel(
   c.vdt = a.vdt;
   c.vdt_f = (float)a.vdt;
   const int kend = T.start + T.count;
-  if (nmin >= 2 * P - 2 && P <= 9) {
-    c.omax = a.L - 1 - 2 * P;
-    switch (P) {
-      case 1: kernel_loop<1>(c, col, T.start, kend); break;
-      case 2: kernel_loop<2>(c, col, T.start, kend); break;
-      case 3: kernel_loop<3>(c, col, T.start, kend); break;
-      case 4: kernel_loop<4>(c, col, T.start, kend); break;
-      case 5: kernel_loop<5>(c, col, T.start, kend); break;
-      case 6: kernel_loop<6>(c, col, T.start, kend); break;
-      case 7: kernel_loop<7>(c, col, T.start, kend); break;
-      case 8: kernel_loop<8>(c, col, T.start, kend); break;
-      default: kernel_loop<9>(c, col, T.start, kend); break;
+  if (nmin >= nmax - 2 && nmax >= 2 && nmax <= 18) {
+    c.omax = a.L - 1 - nmax;
+    switch (nmax) {
+#define GPAIR_FWD_CASE(n) \
+  case n: kernel_loop<n>(c, col, T.start, kend); break;
+      GPAIR_FWD_CASE(2) GPAIR_FWD_CASE(3) GPAIR_FWD_CASE(4) GPAIR_FWD_CASE(5)
+      GPAIR_FWD_CASE(6) GPAIR_FWD_CASE(7) GPAIR_FWD_CASE(8) GPAIR_FWD_CASE(9)
+      GPAIR_FWD_CASE(10) GPAIR_FWD_CASE(11) GPAIR_FWD_CASE(12) GPAIR_FWD_CASE(13)
+      GPAIR_FWD_CASE(14) GPAIR_FWD_CASE(15) GPAIR_FWD_CASE(16) GPAIR_FWD_CASE(17)
+      default: kernel_loop<18>(c, col, T.start, kend); break;
+#undef GPAIR_FWD_CASE
     }
   } else {
     // Widely varying widths inside one tile: per-kernel tap loop.
@@ -337,6 +334,73 @@ __device__ __forceinline__ int wave_max(int x) {
   return x;
 }
 
+// Gather the taps of one kernel-sensor pair from a staged residual row (row
+// points at the pair's first sample): NT samples of which the first nvalid
+// are in the window (only the last three can be outside).  All reads are
+// issued first.
+template <int NT, bool SIG>
+__device__ __forceinline__ void gather_taps(const float *row, float f, float q, float d,
+                                            float rq, float vdt, int nvalid, float &pA,
+                                            float &pS) {
+  float dl[NT];
+#pragma unroll
+  for (int i = 0; i < NT; ++i) dl[i] = row[i];
+#pragma unroll
+  for (int i = (NT - 3 > 0 ? NT - 3 : 0); i < NT; ++i)
+    if (i >= nvalid) dl[i] = 0.0f;
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    const float pd = dl[i] * f * d;
+    pA += pd;
+    if (SIG) pS = fmaf(pd, d * d, pS);
+    d -= vdt;
+    f *= q;
+    q *= rq;
+  }
+}
+
+struct AdjPair {
+  const double4 *sens;
+  const KernelRec *r;
+  const float *stage;
+  const int *nbs;
+  int L, omax, j0;
+  double inv_vdt, t0_over_dt, vdt;
+  float vdt_f;
+};
+
+// The taps of one stage of sensors for one lane's kernel.  NT > 0: every
+// kernel of the wave has NT - 2 .. NT taps (fully unrolled); NT = 0: any.
+template <int NT, bool SIG>
+__device__ __forceinline__ void adjoint_stage(const AdjPair &c, int nsb, float &pA, float &pS) {
+  const KernelRec &r = *c.r;
+  for (int js = 0; js < nsb; ++js) {
+    const double4 s = c.sens[c.j0 + js];
+    const int nb = c.nbs[js];
+    const PairTerms pt = pair_terms(s.x, s.y, s.z, r.cx, r.cy, r.cz, r.h, c.inv_vdt,
+                                    c.t0_over_dt);
+    const float d0 = (float)(pt.fr * c.vdt);
+    const int nvalid = (pt.fr >= r.hlast) ? r.ntap : r.ntap - 1;
+    const int o = min(max(pt.lo - nb, 0), c.omax);
+    const float f = 0.5f * pt.rinv * __builtin_amdgcn_exp2f(r.c * d0 * d0);
+    const float q = __builtin_amdgcn_exp2f(fmaf(r.k1, d0, r.k2));
+    const float *row = c.stage + js * c.L + o;
+    if (NT > 0) {
+      gather_taps<(NT > 0 ? NT : 1), SIG>(row, f, q, d0, r.rq, c.vdt_f, nvalid, pA, pS);
+    } else {
+      float ff = f, qq = q, d = d0;
+      for (int it = 0; it < nvalid; ++it) {
+        const float pd = row[it] * ff * d;
+        pA += pd;
+        if (SIG) pS = fmaf(pd, d * d, pS);
+        d -= c.vdt_f;
+        ff *= qq;
+        qq *= r.rq;
+      }
+    }
+  }
+}
+
 template <int BLOCK, bool SIG>
 __global__ __launch_bounds__(BLOCK) void adjoint_kernel(const double4 *__restrict__ sens,
                                                        AdjArgs a) {
@@ -347,23 +411,35 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(const double4 *__restric
   if (logical >= a.nlogical) return;
   const TileInfo T = a.tiles[logical];
   const int t = threadIdx.x;
+  const int lane = t & (kWave - 1);
+  const int wave = t >> 6;
   const bool live = t < T.count;
   const int64_t i = T.start + (live ? t : 0);
   const KernelRec r = a.krec[i];
 
-  // Taps every lane of the wave has (uniform loop) and the most any has.
-  // A wave with no live lane gets 0 and 0.
-  const int ntail = __builtin_amdgcn_readfirstlane(wave_max(live ? r.ntap : 0));
-  const int nfull = min(ntail, __builtin_amdgcn_readfirstlane(
-                                   wave_min(live ? r.ntap - 1 : 1 << 30)));
-  const float vdt_f = (float)a.vdt;
-  const int omax = a.L - 1 - r.ntap;  // see the forward kernel
-  const int imax = a.L - 1;
+  // Tap-count range of the wave's kernels: selects the unrolled gather.
+  const int nmax = __builtin_amdgcn_readfirstlane(wave_max(live ? r.ntap : 0));
+  const int nmin = __builtin_amdgcn_readfirstlane(wave_min(live ? r.ntap : 1 << 30));
+  const int NT = (nmax >= 2 && nmax <= 18 && nmin >= nmax - 2) ? nmax : 0;
+
+  AdjPair c;
+  c.sens = sens;
+  c.r = &r;
+  c.stage = stage;
+  c.nbs = nbs;
+  c.L = a.L;
+  // By construction every slot a lane reads (its window, plus up to three
+  // padding samples in the unrolled gather) is at most L - 1.
+  c.omax = a.L - (NT > 0 ? NT : r.ntap);
+  c.inv_vdt = a.inv_vdt;
+  c.t0_over_dt = a.t0_over_dt;
+  c.vdt = a.vdt;
+  c.vdt_f = (float)a.vdt;
 
   double accA = 0.0, accS = 0.0;
   for (int j0 = 0; j0 < a.Nd; j0 += kAdjSensorsPerStage) {
     const int nsb = min(kAdjSensorsPerStage, a.Nd - j0);
-    __syncthreads();
+    __syncthreads();  // the previous stage has been consumed
     if (t < nsb) {
       const double4 s = sens[j0 + t];
       const double dx = s.x - T.cx, dy = s.y - T.cy, dz = s.z - T.cz;
@@ -371,47 +447,30 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(const double4 *__restric
       nbs[t] = (int)floor((R - T.rho) * a.inv_vdt - a.t0_over_dt - a.hmax) - 1;
     }
     __syncthreads();
-    for (int idx = t; idx < nsb * a.L; idx += BLOCK) {
-      const int js = idx / a.L;
-      const int n = nbs[js] + (idx - js * a.L);
-      stage[idx] = (n >= 0 && n < a.Nt) ? a.delta[(int64_t)(j0 + js) * a.Nt + n] : 0.0f;
+    // Stage the residual over the tile's time shell: one wave per row, lanes
+    // along the row (coalesced), samples outside the trace read as zero.
+    for (int js = wave; js < nsb; js += BLOCK / kWave) {
+      const float *drow = a.delta + (int64_t)(j0 + js) * a.Nt;
+      const int nb = nbs[js];
+      for (int col = lane; col < a.L; col += kWave) {
+        const int n = nb + col;
+        stage[js * a.L + col] = (n >= 0 && n < a.Nt) ? drow[n] : 0.0f;
+      }
     }
     __syncthreads();
 
+    c.j0 = j0;
     float pA = 0.0f, pS = 0.0f;
-    for (int js = 0; js < nsb; ++js) {
-      const double4 s = sens[j0 + js];
-      const int nb = nbs[js];
-      const PairTerms pt = pair_terms(s.x, s.y, s.z, r.cx, r.cy, r.cz, r.h, a.inv_vdt,
-                                      a.t0_over_dt);
-      const float d0 = (float)(pt.fr * a.vdt);
-      const int nvalid = (pt.fr >= r.hlast) ? r.ntap : r.ntap - 1;
-      int o = pt.lo - nb;
-      o = min(max(o, 0), omax);
-      float f = 0.5f * pt.rinv * __builtin_amdgcn_exp2f(r.c * d0 * d0);
-      float q = __builtin_amdgcn_exp2f(fmaf(r.k1, d0, r.k2));
-      float d = d0;
-      const float *dp = stage + js * a.L + o;
-      int it = 0;
-      for (; it < nfull; ++it) {
-        const float pd = dp[it] * f * d;
-        pA += pd;
-        if (SIG) pS = fmaf(pd, d * d, pS);
-        d -= vdt_f;
-        f *= q;
-        q *= r.rq;
-      }
-      const float *srow = stage + js * a.L;
-      for (; it < ntail; ++it) {
-        // lanes past their own window read an in-range sample and drop it
-        const float dl = (it < nvalid) ? srow[min(o + it, imax)] : 0.0f;
-        const float pd = dl * f * d;
-        pA += pd;
-        if (SIG) pS = fmaf(pd, d * d, pS);
-        d -= vdt_f;
-        f *= q;
-        q *= r.rq;
-      }
+    switch (NT) {
+#define GPAIR_ADJ_CASE(n) \
+  case n: adjoint_stage<n, SIG>(c, nsb, pA, pS); break;
+      GPAIR_ADJ_CASE(2) GPAIR_ADJ_CASE(3) GPAIR_ADJ_CASE(4) GPAIR_ADJ_CASE(5)
+      GPAIR_ADJ_CASE(6) GPAIR_ADJ_CASE(7) GPAIR_ADJ_CASE(8) GPAIR_ADJ_CASE(9)
+      GPAIR_ADJ_CASE(10) GPAIR_ADJ_CASE(11) GPAIR_ADJ_CASE(12) GPAIR_ADJ_CASE(13)
+      GPAIR_ADJ_CASE(14) GPAIR_ADJ_CASE(15) GPAIR_ADJ_CASE(16) GPAIR_ADJ_CASE(17)
+      GPAIR_ADJ_CASE(18)
+      default: adjoint_stage<0, SIG>(c, nsb, pA, pS); break;
+#undef GPAIR_ADJ_CASE
     }
     accA += (double)pA;
     if (SIG) accS += (double)pS;
