@@ -1,0 +1,363 @@
+"""Float64 CPU oracle of the learned warm-start network's layers.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+The warm start is not part of arXiv 2602.03893; it is a small 3D U-Net that
+maps the adjoint (back-projected) image to amplitudes.  Each function below is
+the plain definition of one layer in float64, on arrays in the channels-last
+layout of the GPU path, [N, D, H, W, C].  Inputs are whatever the GPU stores
+(bfloat16 values, passed here as float64), so the oracle's results are the
+exact sums the GPU approximates with float32 accumulation.
+
+Weight layouts (float32 masters, as the GPU path keeps them):
+ - 3x3x3 convolution: w[t][ci][co], t = (dz+1)*9 + (dy+1)*3 + (dx+1), and
+   out[v] = sum_t in[v + (dz, dy, dx)] . w[t] (cross-correlation, zero padding);
+ - 2x2x2 stride-2 transposed convolution: w[t][ci][co], t = tz*4 + ty*2 + tx,
+   and out[2v + (tz, ty, tx)] = in[v] . w[t] + b.
+
+``conv3`` and its gradients use torch's float64 ``conv3d`` as a library step;
+everything else is written out with numpy.  Pins (tests/test_oracle_nn.py):
+brute-force loops on tiny volumes (conv3, maxpool, transposed conv), dot-product
+(adjoint) identities for every data and weight gradient, finite differences of
+the whole network, and torch's ``interpolate`` for the trilinear upsampling.
+"""
+import numpy as np
+import torch
+import torch.nn.functional as F
+
+TAPS3 = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+TAPS2 = [(tz, ty, tx) for tz in (0, 1) for ty in (0, 1) for tx in (0, 1)]
+
+
+def bf16(x):
+    """Round float32-representable values to the nearest bfloat16 (ties to
+    even), returned as float64."""
+    t = torch.as_tensor(np.asarray(x, dtype=np.float32))
+    return t.to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def _to_ncdhw(x):
+    return torch.as_tensor(np.ascontiguousarray(np.moveaxis(np.asarray(x, np.float64), -1, 1)))
+
+
+def _to_ndhwc(t):
+    return np.ascontiguousarray(np.moveaxis(t.detach().numpy(), 1, -1))
+
+
+def _w3_torch(w):
+    """[27][ci][co] -> torch conv3d weight [co][ci][3][3][3]."""
+    w = np.asarray(w, np.float64)
+    ci, co = w.shape[1], w.shape[2]
+    return torch.as_tensor(np.ascontiguousarray(
+        w.reshape(3, 3, 3, ci, co).transpose(4, 3, 0, 1, 2)))
+
+
+def conv3(x, w, b=None, relu=False):
+    """3x3x3 convolution, stride 1, zero padding 1 (+ bias, + ReLU)."""
+    out = F.conv3d(_to_ncdhw(x), _w3_torch(w), padding=1)
+    if b is not None:
+        out = out + torch.as_tensor(np.asarray(b, np.float64)).view(1, -1, 1, 1, 1)
+    if relu:
+        out = torch.clamp(out, min=0.0)
+    return _to_ndhwc(out)
+
+
+def conv3_dgrad(gout, w, mask_act=None):
+    """Input gradient of conv3 for output gradient gout, times (act > 0)."""
+    gout_t = _to_ncdhw(gout)
+    n, co, d, h, wd = gout_t.shape
+    ci = np.asarray(w).shape[1]
+    gin = torch.nn.grad.conv3d_input((n, ci, d, h, wd), _w3_torch(w), gout_t, padding=1)
+    gin = _to_ndhwc(gin)
+    if mask_act is not None:
+        gin = gin * (np.asarray(mask_act) > 0)
+    return gin
+
+
+def conv3_wgrad(x, gout):
+    """dw[t][ci][co] = sum_v x[v + o(t)][ci] gout[v][co]; db[co] = sum_v gout[v][co]."""
+    x_t, g_t = _to_ncdhw(x), _to_ncdhw(gout)
+    ci, co = x_t.shape[1], g_t.shape[1]
+    gw = torch.nn.grad.conv3d_weight(x_t, (co, ci, 3, 3, 3), g_t, padding=1)
+    dw = gw.numpy().transpose(2, 3, 4, 1, 0).reshape(27, ci, co)
+    db = np.asarray(gout, np.float64).reshape(-1, co).sum(axis=0)
+    return np.ascontiguousarray(dw), db
+
+
+def _pool_view(x):
+    """[N, D, H, W, C] -> [N, D/2, H/2, W/2, 8, C] with the 8 children in tap order."""
+    n, d, h, w, c = x.shape
+    v = np.asarray(x).reshape(n, d // 2, 2, h // 2, 2, w // 2, 2, c)
+    v = v.transpose(0, 1, 3, 5, 2, 4, 6, 7)  # n, D, H, W, tz, ty, tx, c
+    return v.reshape(n, d // 2, h // 2, w // 2, 8, c)
+
+
+def maxpool2(x):
+    """2x2x2 max pooling; the argmax is the first child (tap order) holding the max."""
+    v = _pool_view(np.asarray(x, np.float64))
+    arg = np.argmax(v, axis=4)
+    out = np.take_along_axis(v, arg[:, :, :, :, None, :], axis=4)[:, :, :, :, 0, :]
+    return out, arg.astype(np.uint8)
+
+
+def maxpool2_backward(gout, argmax, act, gskip=None):
+    """(gskip + gradient routed to each window's argmax child) * (act > 0)."""
+    n, d2, h2, w2, c = gout.shape
+    routed = np.zeros((n, d2, h2, w2, 8, c))
+    np.put_along_axis(routed, argmax[:, :, :, :, None, :].astype(np.int64),
+                      np.asarray(gout, np.float64)[:, :, :, :, None, :], axis=4)
+    fine = routed.reshape(n, d2, h2, w2, 2, 2, 2, c).transpose(0, 1, 4, 2, 5, 3, 6, 7)
+    fine = fine.reshape(n, 2 * d2, 2 * h2, 2 * w2, c)
+    if gskip is not None:
+        fine = fine + np.asarray(gskip, np.float64)
+    return fine * (np.asarray(act) > 0)
+
+
+def upconv2(x, w, b):
+    """out[2v + (tz,ty,tx)][co] = sum_ci x[v][ci] w[t][ci][co] + b[co]."""
+    x = np.asarray(x, np.float64)
+    n, d, h, wd, ci = x.shape
+    co = np.asarray(w).shape[2]
+    out = np.empty((n, 2 * d, 2 * h, 2 * wd, co))
+    for t, (tz, ty, tx) in enumerate(TAPS2):
+        out[:, tz::2, ty::2, tx::2, :] = x @ np.asarray(w[t], np.float64) + np.asarray(b, np.float64)
+    return out
+
+
+def upconv2_dgrad(gout, w, mask_act=None):
+    """gin[v][ci] = sum_t sum_co gout[2v + t][co] w[t][ci][co] (times act > 0)."""
+    g = np.asarray(gout, np.float64)
+    gin = 0.0
+    for t, (tz, ty, tx) in enumerate(TAPS2):
+        gin = gin + g[:, tz::2, ty::2, tx::2, :] @ np.asarray(w[t], np.float64).T
+    if mask_act is not None:
+        gin = gin * (np.asarray(mask_act) > 0)
+    return gin
+
+
+def upconv2_wgrad(x, gout):
+    """dw[t][ci][co] = sum_v x[v][ci] gout[2v + t][co]; db = sum over fine voxels."""
+    x = np.asarray(x, np.float64)
+    g = np.asarray(gout, np.float64)
+    ci, co = x.shape[-1], g.shape[-1]
+    dw = np.empty((8, ci, co))
+    for t, (tz, ty, tx) in enumerate(TAPS2):
+        dw[t] = x.reshape(-1, ci).T @ g[:, tz::2, ty::2, tx::2, :].reshape(-1, co)
+    return dw, g.reshape(-1, co).sum(axis=0)
+
+
+def head(x, w, b):
+    """1x1x1 convolution to one channel + ReLU: [N, D, H, W]."""
+    return np.maximum(np.asarray(x, np.float64) @ np.asarray(w, np.float64) + float(b), 0.0)
+
+
+def head_backward(x, w, out, gout):
+    """Returns (gin, dw, db) of the head for the output gradient gout."""
+    x = np.asarray(x, np.float64)
+    gp = np.asarray(gout, np.float64) * (np.asarray(out) > 0)
+    gin = gp[..., None] * np.asarray(w, np.float64)[None, None, None, None, :] * (x > 0)
+    dw = (gp[..., None] * x).reshape(-1, x.shape[-1]).sum(axis=0)
+    return gin, dw, gp.sum()
+
+
+def mse(pred, target):
+    """(mean squared error, its gradient 2 (pred - target) / n)."""
+    d = np.asarray(pred, np.float64) - np.asarray(target, np.float64)
+    return float(np.mean(d * d)), 2.0 * d / d.size
+
+
+def _lin_axis(n_in):
+    """Source indices and weights of x2 linear upsampling along one axis
+    (half-voxel aligned, clamped at the edges)."""
+    i = np.arange(2 * n_in)
+    s = np.maximum((i + 0.5) / 2.0 - 0.5, 0.0)
+    i0 = np.minimum(np.floor(s).astype(np.int64), n_in - 1)
+    i1 = np.minimum(i0 + 1, n_in - 1)
+    f = s - i0
+    return i0, i1, f
+
+
+def upsample2(x):
+    """Trilinear x2 upsampling of [N, D, H, W] (separable linear, per axis)."""
+    y = np.asarray(x, np.float64)
+    for ax in (1, 2, 3):
+        i0, i1, f = _lin_axis(y.shape[ax])
+        shape = [1] * y.ndim
+        shape[ax] = -1
+        f = f.reshape(shape)
+        y = (1.0 - f) * np.take(y, i0, axis=ax) + f * np.take(y, i1, axis=ax)
+    return y
+
+
+# ---------------------------------------------------------------------------
+# The U-Net (levels L, base width 16): encoder level l has two 3x3x3 conv +
+# ReLU layers of width 16 * 2^l, then 2x2x2 max pooling; the bottom level
+# has two conv layers; each decoder level upsamples with a transposed conv
+# (no activation), concatenates [upsampled, skip] and applies two conv + ReLU
+# layers; a 1x1x1 head + ReLU gives the output.
+# ---------------------------------------------------------------------------
+
+def unet_layers(levels, base=16):
+    """Parameter list in storage order: (name, kind, taps, c_in, c_out)."""
+    ch = [base * 2 ** l for l in range(levels)]
+    layers = []
+    cin = 1
+    for l in range(levels - 1):
+        layers.append((f"enc{l}a", "conv", 27, cin, ch[l]))
+        layers.append((f"enc{l}b", "conv", 27, ch[l], ch[l]))
+        cin = ch[l]
+    layers.append((f"bot_a", "conv", 27, cin, ch[-1]))
+    layers.append((f"bot_b", "conv", 27, ch[-1], ch[-1]))
+    for l in range(levels - 2, -1, -1):
+        layers.append((f"up{l}", "up", 8, ch[l + 1], ch[l]))
+        layers.append((f"dec{l}a", "conv", 27, 2 * ch[l], ch[l]))
+        layers.append((f"dec{l}b", "conv", 27, ch[l], ch[l]))
+    layers.append(("head", "head", 1, ch[0], 1))
+    return layers
+
+
+def unpack_params(levels, flat):
+    """Flat float32 parameter vector -> {name: (w, b)}; w is [taps][ci][co]
+    (the head's is [ci]), b is [co]; each layer stores w then b."""
+    out = {}
+    off = 0
+    for name, kind, taps, ci, co in unet_layers(levels):
+        nw = taps * ci * co
+        w = np.asarray(flat[off:off + nw], np.float64)
+        off += nw
+        b = np.asarray(flat[off:off + co], np.float64)
+        off += co
+        out[name] = (w.reshape(ci) if kind == "head" else w.reshape(taps, ci, co), b)
+    return out, off
+
+
+def unet_forward(levels, params, x, round_bf16=True):
+    """Forward pass on x [N, D, H, W] (float), returning (y [N, D, H, W], acts).
+
+    With round_bf16, the input, every weight used in bfloat16 and every stored
+    activation are rounded to bfloat16 exactly where the GPU path stores them;
+    the arithmetic in between is exact (float64).  acts holds every stored
+    activation (the backward's inputs)."""
+    r = bf16 if round_bf16 else (lambda a: np.asarray(a, np.float64))
+    p, _ = unpack_params(levels, params)
+    acts = {}
+    h = r(np.asarray(x, np.float64)[..., None])
+    acts["in"] = h
+    for l in range(levels - 1):
+        w, b = p[f"enc{l}a"]
+        acts[f"a{l}"] = h = r(conv3(h, r(w), b, relu=True))
+        w, b = p[f"enc{l}b"]
+        acts[f"e{l}"] = h = r(conv3(h, r(w), b, relu=True))
+        h, acts[f"arg{l}"] = maxpool2(h)
+        acts[f"p{l}"] = h
+    w, b = p["bot_a"]
+    acts["bota"] = h = r(conv3(h, r(w), b, relu=True))
+    w, b = p["bot_b"]
+    acts["botb"] = h = r(conv3(h, r(w), b, relu=True))
+    for l in range(levels - 2, -1, -1):
+        w, b = p[f"up{l}"]
+        u = r(upconv2(h, r(w), b))
+        acts[f"cat{l}"] = h = np.concatenate([u, acts[f"e{l}"]], axis=-1)
+        w, b = p[f"dec{l}a"]
+        acts[f"da{l}"] = h = r(conv3(h, r(w), b, relu=True))
+        w, b = p[f"dec{l}b"]
+        acts[f"db{l}"] = h = r(conv3(h, r(w), b, relu=True))
+    w, b = p["head"]
+    y = head(h, w, b[0])
+    acts["y"] = y
+    return y, acts
+
+
+def unet_backward(levels, params, x, gy, round_bf16=True):
+    """Gradient of sum(gy * y) with respect to the flat parameter vector,
+    by the chain rule through the layers of ``unet_forward`` in reverse order.
+    With round_bf16 every activation gradient is rounded to bfloat16 where the
+    GPU path stores it (weight and bias gradients stay exact)."""
+    r = bf16 if round_bf16 else (lambda a: np.asarray(a, np.float64))
+    p, n_par = unpack_params(levels, params)
+    _, A = unet_forward(levels, params, x, round_bf16)
+    grads = {}
+    hlast = A["db0"] if levels >= 2 else A["botb"]
+    w, _ = p["head"]
+    gin, dw, db = head_backward(hlast, w, A["y"], gy)
+    grads["head"] = (dw, np.array([db]))
+    g = r(gin)
+    skip = {}
+    for l in range(levels - 1):
+        C = 16 * 2 ** l
+        grads[f"dec{l}b"] = conv3_wgrad(A[f"da{l}"], g)
+        g_da = r(conv3_dgrad(g, r(p[f"dec{l}b"][0]), mask_act=A[f"da{l}"]))
+        grads[f"dec{l}a"] = conv3_wgrad(A[f"cat{l}"], g_da)
+        g_cat = r(conv3_dgrad(g_da, r(p[f"dec{l}a"][0])))
+        skip[l] = g_cat[..., C:]
+        hin = A[f"db{l + 1}"] if l + 1 <= levels - 2 else A["botb"]
+        grads[f"up{l}"] = upconv2_wgrad(hin, g_cat[..., :C])
+        g = r(upconv2_dgrad(g_cat[..., :C], r(p[f"up{l}"][0]), mask_act=hin))
+    grads["bot_b"] = conv3_wgrad(A["bota"], g)
+    g_ba = r(conv3_dgrad(g, r(p["bot_b"][0]), mask_act=A["bota"]))
+    in_b = A[f"p{levels - 2}"] if levels >= 2 else A["in"]
+    grads["bot_a"] = conv3_wgrad(in_b, g_ba)
+    if levels >= 2:
+        g_p = r(conv3_dgrad(g_ba, r(p["bot_a"][0])))
+    for l in range(levels - 2, -1, -1):
+        g_e = r(maxpool2_backward(g_p, A[f"arg{l}"], A[f"e{l}"], gskip=skip[l]))
+        grads[f"enc{l}b"] = conv3_wgrad(A[f"a{l}"], g_e)
+        g_a = r(conv3_dgrad(g_e, r(p[f"enc{l}b"][0]), mask_act=A[f"a{l}"]))
+        in_l = A["in"] if l == 0 else A[f"p{l - 1}"]
+        grads[f"enc{l}a"] = conv3_wgrad(in_l, g_a)
+        if l > 0:
+            g_p = r(conv3_dgrad(g_a, r(p[f"enc{l}a"][0])))
+    flat = np.empty(n_par)
+    off = 0
+    for name, kind, taps, ci, co in unet_layers(levels):
+        dw, db = grads[name]
+        nw = taps * ci * co
+        flat[off:off + nw] = np.asarray(dw).reshape(-1)
+        off += nw
+        flat[off:off + co] = np.asarray(db).reshape(-1)
+        off += co
+    return flat
+
+
+def unet_loss_and_grad(levels, params, x, target):
+    """MSE loss of the network on (x, target) and its gradient with respect to
+    the flat parameter vector, in float64 by autograd on the plain torch
+    formulation of the same layers (no bfloat16 rounding)."""
+    flat = torch.tensor(np.asarray(params, np.float64), requires_grad=True)
+    layers = unet_layers(levels)
+    views = {}
+    off = 0
+    for name, kind, taps, ci, co in layers:
+        nw = taps * ci * co
+        w = flat[off:off + nw]
+        off += nw
+        b = flat[off:off + co]
+        off += co
+        views[name] = (w, b, kind, taps, ci, co)
+
+    def conv(h, name):
+        w, b, _, _, ci, co = views[name]
+        wt = w.view(3, 3, 3, ci, co).permute(4, 3, 0, 1, 2)
+        return torch.relu(F.conv3d(h, wt, b, padding=1))
+
+    def up(h, name):
+        w, b, _, _, ci, co = views[name]
+        # conv_transpose3d weight [ci][co][kz][ky][kx]; tap t = kz*4 + ky*2 + kx
+        wt = w.view(2, 2, 2, ci, co).permute(3, 4, 0, 1, 2)
+        return F.conv_transpose3d(h, wt, b, stride=2)
+
+    h = torch.as_tensor(np.asarray(x, np.float64))[:, None]
+    skips = []
+    for l in range(levels - 1):
+        h = conv(conv(h, f"enc{l}a"), f"enc{l}b")
+        skips.append(h)
+        h = F.max_pool3d(h, 2)
+    h = conv(conv(h, "bot_a"), "bot_b")
+    for l in range(levels - 2, -1, -1):
+        h = torch.cat([up(h, f"up{l}"), skips[l]], dim=1)
+        h = conv(conv(h, f"dec{l}a"), f"dec{l}b")
+    w, b, *_ = views["head"]
+    y = torch.relu(torch.einsum("ncdhw,c->ndhw", h, w) + b[0])
+    loss = torch.mean((y - torch.as_tensor(np.asarray(target, np.float64))) ** 2)
+    loss.backward()
+    return float(loss.detach()), flat.grad.numpy().copy(), y.detach().numpy()
