@@ -266,6 +266,37 @@ gpair_status gpair_adam_update(int64_t n, float *x, const float *g, float *m,
                                float lo, float hi, gpair_stream stream);
 
 /* ------------------------------------------------------------------------ */
+/* a8 (last step). Least-squares rescale of a warm start, with fallback        */
+/* ------------------------------------------------------------------------ */
+
+typedef struct gpair_warm_report {
+  double c_star;     /* the scale applied (0 when the start fell back)        */
+  double rho;        /* ||A(c* x) - b|| / ||b|| (1 when it fell back)         */
+  int32_t fell_back; /* 1: A was set to zero (the zero start, rho = 1)        */
+  int32_t pad;
+} gpair_warm_report;
+
+/*
+ * Rescale a candidate start x (for instance a learned or back-projected
+ * image) by the least-squares factor c* = max(0, <A x, b> / ||A x||^2), the
+ * scale that minimises ||A(c x) - b|| over c >= 0, so that the rescaled start
+ * is never worse than the zero start (rho(0) = 1).  When c* = 0 or the
+ * rescaled relative residual is not below 1 the start is replaced by zero.
+ * The relative residual rho is the one of Algorithm 2's loss.
+ *  A         device float32 [n_kernels]: x on entry, c* x (or 0) on return.
+ *  sigma     device float32 [n_kernels].
+ *  b         device float32 [n_sensors][n_samples], ||b|| > 0.
+ *  y_scratch device float32 [n_sensors][n_samples]: receives A x.
+ *  report    host, filled on success.
+ * Synchronises `stream` (the fallback is decided on the host).  Errors:
+ * INVALID_ARG (also for b = 0), NONFINITE (a non-finite dot product; A is
+ * then left unchanged), HIP.
+ */
+gpair_status gpair_warm_rescale(gpair_plan p, float *A, const float *sigma, const float *b,
+                                float *y_scratch, gpair_warm_report *report,
+                                gpair_stream stream);
+
+/* ------------------------------------------------------------------------ */
 /* a6. Iterative reconstruction driver                                        */
 /* ------------------------------------------------------------------------ */
 

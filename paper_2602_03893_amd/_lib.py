@@ -110,6 +110,12 @@ gpair_solve_workspace_size = _proto("gpair_solve_workspace_size", c_i32,
 gpair_solve = _proto("gpair_solve", c_i32,
                      [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(SolveOpts), c_vp,
                       ctypes.c_size_t, ctypes.POINTER(SolveReport), c_vp])
+class WarmReport(ctypes.Structure):
+    _fields_ = [("c_star", c_dbl), ("rho", c_dbl), ("fell_back", c_i32), ("pad", c_i32)]
+
+
+gpair_warm_rescale = _proto("gpair_warm_rescale", c_i32,
+                            [c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(WarmReport), c_vp])
 gpair_plan_set_timing = _proto("gpair_plan_set_timing", c_i32, [c_vp, ctypes.c_int])
 gpair_plan_kernel_times = _proto("gpair_plan_kernel_times", c_i32,
                                  [c_vp, ctypes.c_int, c_fp, c_i32, ctypes.POINTER(c_i32)])

@@ -148,6 +148,20 @@ class Plan:
               "gpair_residual")
         return norms
 
+    def warm_rescale(self, A, sigma, b, y_scratch=None):
+        """Rescale the start A in place by c* = max(0, <A x, b>/||A x||^2), or
+        zero it when that does not beat the zero start; returns the report."""
+        n = self.n_sensors * self.n_samples
+        if y_scratch is None:
+            y_scratch = torch.empty(n, dtype=torch.float32, device=self.device)
+        rep = _lib.WarmReport()
+        check(_lib.gpair_warm_rescale(
+            self._h, _dev(A, "A", self.n_kernels, device=self.device),
+            _dev(sigma, "sigma", self.n_kernels, device=self.device),
+            _dev(b, "b", n, device=self.device), _dev(y_scratch, "y_scratch", n, device=self.device),
+            ctypes.byref(rep), _stream()), "gpair_warm_rescale")
+        return {"c_star": rep.c_star, "rho": rep.rho, "fell_back": bool(rep.fell_back)}
+
     def sigma_violations(self):
         n = ctypes.c_int64()
         check(_lib.gpair_sigma_violations(self._h, ctypes.byref(n), _stream()),

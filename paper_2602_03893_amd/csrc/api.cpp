@@ -192,6 +192,41 @@ gpair_status gpair_residual(gpair_plan p, const float *y, const float *b, float 
   return hip_status(launch_residual(p, y, b, scale, delta, norms, (hipStream_t)stream));
 }
 
+gpair_status gpair_warm_rescale(gpair_plan p, float *A, const float *sigma, const float *b,
+                                float *y_scratch, gpair_warm_report *report,
+                                gpair_stream stream) {
+  if (!bound(p) || !A || !sigma || !b || !y_scratch || !report) return GPAIR_ERR_INVALID_ARG;
+  const hipStream_t s = (hipStream_t)stream;
+  gpair_status st = gpair_forward(p, A, sigma, y_scratch, stream);
+  if (st != GPAIR_OK) return st;
+  double *dots = ws_partials(p) + 3 * kResidualBlocks;  // the 64-byte tail
+  if (launch_dot3(p, y_scratch, b, dots, s) != hipSuccess) return GPAIR_ERR_HIP;
+  double h[3];
+  if (hipMemcpyAsync(h, dots, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return GPAIR_ERR_HIP;
+  const double yb = h[0], yy = h[1], bb = h[2];
+  if (!std::isfinite(yb) || !std::isfinite(yy) || !std::isfinite(bb)) return GPAIR_ERR_NONFINITE;
+  if (!(bb > 0.0)) return GPAIR_ERR_INVALID_ARG;
+  const int64_t M = p->M;
+  double c = (yy > 0.0 && yb > 0.0) ? yb / yy : 0.0;
+  // ||c y - b||^2 / ||b||^2 at the optimal c: 1 - <y,b>^2 / (||y||^2 ||b||^2)
+  double rho = c > 0.0 ? std::sqrt(std::fmax(0.0, 1.0 - (yb / yy) * (yb / bb))) : 1.0;
+  const bool fall = !(c > 0.0) || !(rho < 1.0);
+  if (fall) {
+    c = 0.0;
+    rho = 1.0;
+    if (launch_fill(A, M, 0.0f, s) != hipSuccess) return GPAIR_ERR_HIP;
+  } else if (launch_scale(A, M, (float)c, s) != hipSuccess) {
+    return GPAIR_ERR_HIP;
+  }
+  report->c_star = c;
+  report->rho = rho;
+  report->fell_back = fall ? 1 : 0;
+  report->pad = 0;
+  return GPAIR_OK;
+}
+
 gpair_status gpair_pgd_update(int64_t n, float *x, const float *g, float step, float lo,
                               float hi, gpair_stream stream) {
   if (n < 0 || (n > 0 && (!x || !g)) || !std::isfinite(step) || std::isnan(lo) ||

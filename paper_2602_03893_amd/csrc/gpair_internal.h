@@ -97,6 +97,11 @@ namespace gpair {
 hipError_t launch_prep(const gpair_plan_s *p, const float *A, const float *sigma,
                        hipStream_t s);
 hipError_t launch_fill(float *x, int64_t n, float value, hipStream_t s);
+hipError_t launch_scale(float *x, int64_t n, float alpha, hipStream_t s);
+// (<y, b>, ||y||^2, ||b||^2) in float64, fixed summation order, into out[3]
+// (device); partial sums in the plan workspace.
+hipError_t launch_dot3(const gpair_plan_s *p, const float *y, const float *b, double *out,
+                       hipStream_t s);
 hipError_t launch_forward(const gpair_plan_s *p, float *y, hipStream_t s);
 hipError_t launch_adjoint(const gpair_plan_s *p, const float *delta, float *gA,
                           float *gsigma, hipStream_t s);

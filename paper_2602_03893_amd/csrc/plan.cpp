@@ -174,7 +174,7 @@ WorkspaceLayout layout_for(int64_t M, int32_t Nd, size_t nft, size_t nat) {
   l.atiles = off;   off = align256(off + nat * sizeof(TileInfo));
   l.krec = off;     off = align256(off + (size_t)M * sizeof(KernelRec));
   l.counters = off; off = align256(off + 64);
-  l.partials = off; off = align256(off + (size_t)kResidualBlocks * 2 * sizeof(double) + 64);
+  l.partials = off; off = align256(off + (size_t)kResidualBlocks * 3 * sizeof(double) + 64);
   l.total = off;
   return l;
 }

@@ -75,6 +75,72 @@ __global__ __launch_bounds__(kVecBlock) void residual_final_kernel(
   }
 }
 
+__global__ __launch_bounds__(kVecBlock) void scale_kernel(float *__restrict__ x, int64_t n,
+                                                          float alpha) {
+  const int64_t stride = (int64_t)gridDim.x * kVecBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kVecBlock + threadIdx.x; i < n; i += stride)
+    x[i] = alpha * x[i];
+}
+
+// Block-wide float64 sum of three values in a fixed tree order.
+__device__ __forceinline__ void block_sum3(double &a, double &b, double &c, double *sh) {
+  const int t = threadIdx.x;
+  sh[t] = a;
+  sh[kVecBlock + t] = b;
+  sh[2 * kVecBlock + t] = c;
+  __syncthreads();
+  for (int w = kVecBlock / 2; w > 0; w >>= 1) {
+    if (t < w) {
+      sh[t] += sh[t + w];
+      sh[kVecBlock + t] += sh[kVecBlock + t + w];
+      sh[2 * kVecBlock + t] += sh[2 * kVecBlock + t + w];
+    }
+    __syncthreads();
+  }
+  a = sh[0];
+  b = sh[kVecBlock];
+  c = sh[2 * kVecBlock];
+}
+
+__global__ __launch_bounds__(kVecBlock) void dot3_partial_kernel(const float *__restrict__ y,
+                                                                 const float *__restrict__ b,
+                                                                 int64_t n,
+                                                                 double *__restrict__ partials) {
+  __shared__ double sh[3 * kVecBlock];
+  double yb = 0.0, yy = 0.0, bb = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kVecBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kVecBlock + threadIdx.x; i < n; i += stride) {
+    const double yi = y[i], bi = b[i];
+    yb += yi * bi;
+    yy += yi * yi;
+    bb += bi * bi;
+  }
+  block_sum3(yb, yy, bb, sh);
+  if (threadIdx.x == 0) {
+    partials[3 * blockIdx.x] = yb;
+    partials[3 * blockIdx.x + 1] = yy;
+    partials[3 * blockIdx.x + 2] = bb;
+  }
+}
+
+__global__ __launch_bounds__(kVecBlock) void dot3_final_kernel(const double *__restrict__ partials,
+                                                               int nparts,
+                                                               double *__restrict__ out) {
+  __shared__ double sh[3 * kVecBlock];
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kVecBlock) {
+    a += partials[3 * i];
+    b += partials[3 * i + 1];
+    c += partials[3 * i + 2];
+  }
+  block_sum3(a, b, c, sh);
+  if (threadIdx.x == 0) {
+    out[0] = a;
+    out[1] = b;
+    out[2] = c;
+  }
+}
+
 __global__ __launch_bounds__(kVecBlock) void pgd_kernel(float *__restrict__ x,
                                                         const float *__restrict__ g,
                                                         int64_t n, float step, float lo,
@@ -117,6 +183,20 @@ hipError_t launch_residual(const gpair_plan_s *p, const float *y, const float *b
   residual_partial_kernel<<<kResidualBlocks, kVecBlock, 0, s>>>(y, b, scale, delta, n,
                                                                partials);
   residual_final_kernel<<<1, kVecBlock, 0, s>>>(partials, kResidualBlocks, norms);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(float *x, int64_t n, float alpha, hipStream_t s) {
+  scale_kernel<<<vec_grid(n), kVecBlock, 0, s>>>(x, n, alpha);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot3(const gpair_plan_s *p, const float *y, const float *b, double *out,
+                       hipStream_t s) {
+  const int64_t n = (int64_t)p->Nd * p->Nt;
+  double *partials = ws_partials(p);
+  dot3_partial_kernel<<<kResidualBlocks, kVecBlock, 0, s>>>(y, b, n, partials);
+  dot3_final_kernel<<<1, kVecBlock, 0, s>>>(partials, kResidualBlocks, out);
   return hipGetLastError();
 }
 

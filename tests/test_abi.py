@@ -9,19 +9,23 @@ import pytest
 
 from tests.conftest import ROOT
 
-HEADER = os.path.join(ROOT, "include", "gpair.h")
+HEADERS = [os.path.join(ROOT, "include", h)
+           for h in sorted(os.listdir(os.path.join(ROOT, "include"))) if h.endswith(".h")]
 
 
 def header_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(gpair_[a-z0-9_]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names.update(re.findall(r"\b(gpair_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
     names = header_functions()
     for required in ("gpair_plan_create", "gpair_forward", "gpair_adjoint", "gpair_solve",
-                     "gpair_residual", "gpair_adam_update", "gpair_pgd_update"):
+                     "gpair_residual", "gpair_adam_update", "gpair_pgd_update",
+                     "gpair_nn_conv3", "gpair_nn_conv3_wgrad", "gpair_nn_upconv2"):
         assert required in names
 
 
