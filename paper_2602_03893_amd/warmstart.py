@@ -47,7 +47,7 @@ def _phantom_job(seed):
 class Problem:
     """Full- and half-resolution plans of the paper-scale acquisition."""
 
-    def __init__(self, device="cuda"):
+    def __init__(self, device=None):
         import torch
         from .api import Plan
         self.torch = torch
