@@ -33,7 +33,7 @@ FLOP_PAIR = 25        # distance (3 sub, 3 fma, sqrt), window bounds, 1/(2r), ta
 # by the sha256 prefix of the kernel source they were measured on; when the source
 # differs, the figure no longer applies and `traffic` is null.
 MEASURED_TRAFFIC = {
-    "e030a14f1607367e": {"forward_kernel": 5.396e9, "adjoint_kernel": 0.697e9},
+    "5d9f18fee781f2c5": {"forward_kernel": 5.396e9, "adjoint_kernel": 0.696e9},
 }
 
 
@@ -76,6 +76,122 @@ def cpu_baseline(w, centres, sensors, A, sigma_val, rows=32, stride=32):
                        f"sensors ({t_adj:.2f} s); rate = pairs / time")}
 
 
+PEAK_BF16_TFLOPS = 2500.0  # MI355X dense bf16 matrix peak (published)
+
+
+def net_flops(levels, n, d, h, w):
+    """Algorithmic FLOPs of one training step of the warm-start U-Net (forward,
+    data gradients, weight gradients; 2 per multiply-add) and of its forward."""
+    fwd = bwd = 0.0
+    vox = lambda l: n * (d >> l) * (h >> l) * (w >> l)
+    ch = lambda l: 16 << l
+    convs = []  # (level, cin, cout, taps, first)
+    cin = 1
+    for l in range(levels - 1):
+        convs += [(l, cin, ch(l), 27, cin == 1), (l, ch(l), ch(l), 27, False)]
+        cin = ch(l)
+    convs += [(levels - 1, cin, ch(levels - 1), 27, cin == 1),
+              (levels - 1, ch(levels - 1), ch(levels - 1), 27, False)]
+    for l in range(levels - 2, -1, -1):
+        convs += [(l + 1, ch(l + 1), ch(l), 8, False),   # transposed conv, per coarse voxel
+                  (l, 2 * ch(l), ch(l), 27, False), (l, ch(l), ch(l), 27, False)]
+    for lvl, ci, co, taps, first in convs:
+        f = 2.0 * vox(lvl) * taps * ci * co
+        fwd += f
+        bwd += f * (1 if first else 2)
+    return fwd + bwd, fwd
+
+
+def bench_net(args):
+    """The warm-start U-Net: one training step (forward, MSE, backward, Adam)
+    on a batch of 4 volumes of 64 x 128 x 128, and the dominant convolution
+    (the 32 -> 16 decoder conv at full resolution) timed alone."""
+    import numpy as np
+    import torch
+    from paper_2602_03893_amd import inputs as I
+    from paper_2602_03893_amd import nn as m
+    levels, shape = 4, (4, 64, 128, 128)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    x = torch.as_tensor(np.abs(I.standard_normal(shape, seed=5))).to(dev)
+    t = torch.as_tensor(np.abs(I.standard_normal(shape, seed=6))).to(dev)
+    net = m.UNet(levels, shape, seed=1, device=dev)
+    for _ in range(args.warmup):
+        net.train_step(x, t, 1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        net.train_step(x, t, 1e-4)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms = 1e3 * elapsed / args.steps
+    flop, flop_fwd = net_flops(levels, *shape)
+    # dominant layer alone: events on the stream the kernel is launched on
+    n, d, h, w = shape
+    cin, cout = 32, 16
+    xin = torch.randn((n, d, h, w, cin), device=dev).relu_().to(torch.bfloat16)
+    wm = torch.randn((27, cin, cout), device=dev) * (2.0 / (27 * cin)) ** 0.5
+    wf = torch.empty((27, cout, cin), dtype=torch.bfloat16, device=dev)
+    m.pack_weights(wm, 27, cin, cout, wf)
+    bias = torch.zeros(cout, device=dev)
+    out = torch.empty((n, d, h, w, cout), dtype=torch.bfloat16, device=dev)
+    for _ in range(3):
+        m.conv3(xin, wf, bias, out)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record(s)
+    for _ in range(reps):
+        m.conv3(xin, wf, bias, out)
+    e1.record(s)
+    torch.cuda.synchronize()
+    conv_ms = e0.elapsed_time(e1) / reps
+    conv_flop = 2.0 * n * d * h * w * 27 * cin * cout
+    achieved = conv_flop / (conv_ms * 1e-3) / 1e12
+    vox = n * d * h * w
+    log(f"bench: U-Net train step {ms:.2f} ms ({flop / (ms * 1e-3) / 1e12:.1f} TFLOP/s), "
+        f"conv 32->16 at 4x64x128x128 {conv_ms:.3f} ms ({achieved:.1f} TFLOP/s)")
+    # the learned warm start at the paper-scale acquisition (half-resolution
+    # adjoint, network, upsampling, rescale forward and dot products)
+    from paper_2602_03893_amd import warmstart as W
+    prob = W.Problem(device=dev)
+    wpath = os.path.join(ROOT, "paper_2602_03893_amd", "weights", "unet4_c4.npy")
+    params = np.load(wpath, allow_pickle=False) if os.path.exists(wpath) else \
+        m.unet_init_params(levels, 1).numpy()
+    kappa = W.TRAINED_KAPPA
+    ws = m.WarmStart(prob.full, prob.half, levels, params, prob.vol_half, 1.0 / kappa)
+    _, xs, _ = W.phantom_sample(100010)
+    bw = prob.traces(xs, 100010)
+    for _ in range(2):
+        ws(bw, prob.sig_full, prob.sig_half)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(5):
+        _, rep = ws(bw, prob.sig_full, prob.sig_half)
+    torch.cuda.synchronize()
+    warm_ms = 1e3 * (time.perf_counter() - t1) / 5
+    log(f"bench: warm start {warm_ms:.2f} ms (rho {rep['rho']:.4f})")
+    out = {
+        "metric": "warm-start U-Net training voxels/s",
+        "value": vox * args.steps / elapsed,
+        "unit": "voxels/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 (f32 accumulate, f32 master weights)",
+        "data": "synthetic (seeded |N(0,1)| volumes)",
+        "config": {"workload": "4-level 3D U-Net (16-128 channels), batch 4 x 64x128x128, "
+                               "forward + MSE + backward + Adam",
+                   "parameters": m.unet_param_count(levels), "parallelism": "single GPU"},
+        "train_tflops": flop / (ms * 1e-3) / 1e12,
+        "warm_start_ms": warm_ms,
+        "warm_start_rho": rep["rho"],
+        "roofline": {"bound": "mfma", "kernel": "conv_mfma_kernel<32,16> (32->16, 4x64x128x128)",
+                     "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +199,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="paper")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--net", action="store_true",
+                    help="benchmark the warm-start U-Net training step instead")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 256 MiB device buffer 3 times (scale reference "
                          "for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -101,6 +219,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "kernel-sharded path is a design, not part of this build", file=sys.stderr)
         sys.exit(2)
+    if args.net:
+        bench_net(args)
+        return
 
     import numpy as np
     import torch

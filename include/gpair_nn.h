@@ -20,8 +20,14 @@
  *    bfloat16 [8][C_out][C_in], tap t = (z%2)*4 + (y%2)*2 + (x%2) of the
  *    output voxel.  Master weights are float32 [taps][C_in][C_out] (the
  *    layout gpair_nn_pack_weights reads).
- *  - Supported channel counts: C_in in {1, 16, 32, 64, 128} for 3x3x3
- *    convolutions, {16, 32, 64, 128} elsewhere; C_out in {16, 32, 64, 128}.
+ *  - Supported channel counts: 3x3x3 convolution C_in in {1, 16, 32, 64,
+ *    128} and C_out in {16, 32, 64, 128} (C_in = 1: C_out in {16, 32}, no
+ *    MASK epilogue); transposed convolution C_in in {32, 64, 128}, C_out in
+ *    {16, 32, 64}; max pooling C in {16, 32, 64, 128}; head C in {16, 32}.
+ *  - Views with C > 1 need a 16-byte aligned data pointer and a channel
+ *    stride that is a multiple of 8 (8 channels are one 16-byte access).
+ *  - An output must not overlap an input of the same call, except where a
+ *    call says so.
  *  - All pointers are device memory owned by the caller; work goes on
  *    `stream`; shapes are validated on the host (GPAIR_ERR_INVALID_ARG,
  *    nothing launched).  Launch failures return GPAIR_ERR_HIP.

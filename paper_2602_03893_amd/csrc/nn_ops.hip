@@ -441,32 +441,67 @@ __global__ __launch_bounds__(kConvBlock) void wgrad_kernel(WgradArgs a) {
   }
 }
 
-// dw[t][0][co] of the single-channel first layer: thread (t, co) sums over
-// its split's voxels.
-__global__ __launch_bounds__(448) void wgrad_c1_kernel(const uint16_t *__restrict__ in,
-                                                       int64_t in_cs,
-                                                       const uint16_t *__restrict__ gout,
-                                                       int64_t gout_cs, Grid g, int cout,
-                                                       int nsplit, float *__restrict__ partial) {
-  const int pair = blockIdx.y * 448 + threadIdx.x;
-  if (pair >= 27 * cout) return;
-  const int t = pair / cout, co = pair % cout;
-  const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+// dw[t][0][co] of the single-channel first layer on the matrix cores:
+// D[tap][co] = sum_v T[tap][v] F[co][v] with T[tap][v] = in[v + o(tap)] (rows
+// 27..31 zero) and F = gout transposed, both staged per 64-voxel chunk.
+template <int CO>
+__global__ __launch_bounds__(kConvBlock) void wgrad_c1_kernel(const uint16_t *__restrict__ in,
+                                                              int64_t in_cs,
+                                                              const uint16_t *__restrict__ gout,
+                                                              int64_t gout_cs, Grid g,
+                                                              int nsplit,
+                                                              float *__restrict__ partial) {
+  constexpr int NB = CO / 16;
+  constexpr int TILES = 2 * NB;  // two 16-row blocks of taps
+  __shared__ __align__(16) uint16_t ldsT[32 * kLdsRow];
+  __shared__ __align__(16) uint16_t ldsF[CO * kLdsRow];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int r = lane & 15, q = lane >> 4;
   const int D = 1 << g.ld, H = 1 << g.lh, W = 1 << g.lw;
-  const int64_t per = (g.nvox + nsplit - 1) / nsplit;
-  const int64_t v0 = (int64_t)blockIdx.x * per;
-  const int64_t v1 = v0 + per < g.nvox ? v0 + per : g.nvox;
-  const int64_t toff = ((int64_t)dz << (g.lw + g.lh)) + ((int64_t)dy << g.lw) + dx;
-  float acc = 0.f;
-  for (int64_t v = v0; v < v1; ++v) {
-    const int x = (int)(v & (W - 1)), y = (int)((v >> g.lw) & (H - 1)),
-              z = (int)((v >> (g.lw + g.lh)) & (D - 1));
-    if ((unsigned)(z + dz) >= (unsigned)D || (unsigned)(y + dy) >= (unsigned)H ||
-        (unsigned)(x + dx) >= (unsigned)W)
-      continue;
-    acc = fmaf(bf2f(in[(v + toff) * in_cs]), bf2f(gout[v * gout_cs + co]), acc);
+  const int64_t nchunks = (g.nvox + kChunk - 1) / kChunk;
+  for (int i = threadIdx.x; i < 5 * kLdsRow; i += kConvBlock) ldsT[27 * kLdsRow + i] = 0;
+  f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t chunk = blockIdx.x; chunk < nchunks; chunk += nsplit) {
+    const int64_t c0 = chunk * kChunk;
+    __syncthreads();
+    stage_T<CO>(ldsF, [&](int i) -> const uint16_t * {
+      const int64_t v = c0 + i;
+      return v < g.nvox ? gout + v * gout_cs : nullptr;
+    });
+    for (int idx = threadIdx.x; idx < 27 * kChunk; idx += kConvBlock) {
+      const int t = idx / kChunk, i = idx % kChunk;
+      const int64_t v = c0 + i;
+      uint16_t val = 0;
+      if (v < g.nvox) {
+        const int x = (int)(v & (W - 1)), y = (int)((v >> g.lw) & (H - 1)),
+                  z = (int)((v >> (g.lw + g.lh)) & (D - 1));
+        const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+        if ((unsigned)(z + dz) < (unsigned)D && (unsigned)(y + dy) < (unsigned)H &&
+            (unsigned)(x + dx) < (unsigned)W)
+          val = in[(v + ((int64_t)dz << (g.lw + g.lh)) + ((int64_t)dy << g.lw) + dx) * in_cs];
+      }
+      ldsT[t * kLdsRow + i] = val;
+    }
+    __syncthreads();
+    if (wave < TILES) {
+      const int mb = wave / NB, nb = wave % NB;
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        const u32x4 av = ld16(ldsT + (16 * mb + r) * kLdsRow + 32 * ks + 8 * q);
+        const u32x4 bv = ld16(ldsF + (16 * nb + r) * kLdsRow + 32 * ks + 8 * q);
+        acc = mfma16(av, bv, acc);
+      }
+    }
   }
-  partial[(int64_t)blockIdx.x * 27 * cout + pair] = acc;
+  if (wave < TILES) {
+    const int mb = wave / NB, nb = wave % NB;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int t = 16 * mb + 4 * q + k;
+      if (t < 27) partial[((int64_t)blockIdx.x * 27 + t) * CO + 16 * nb + r] = acc[k];
+    }
+  }
 }
 
 // out[e] = sum_s partial[s][e], s ascending.
@@ -911,9 +946,10 @@ hipError_t launch_wgrad(const WgradArgs &a, int mode, int cin, int cout, float *
 hipError_t launch_wgrad_c1(const uint16_t *in, int64_t in_cs, const uint16_t *gout,
                            int64_t gout_cs, const Grid &g, int cout, float *partial,
                            int nsplit, float *dw, hipStream_t s) {
-  const unsigned ny = (unsigned)((27 * cout + 447) / 448);
-  wgrad_c1_kernel<<<dim3((unsigned)nsplit, ny), 448, 0, s>>>(in, in_cs, gout, gout_cs, g, cout,
-                                                             nsplit, partial);
+  if (cout == 16)
+    wgrad_c1_kernel<16><<<nsplit, kConvBlock, 0, s>>>(in, in_cs, gout, gout_cs, g, nsplit, partial);
+  else
+    wgrad_c1_kernel<32><<<nsplit, kConvBlock, 0, s>>>(in, in_cs, gout, gout_cs, g, nsplit, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t n = 27 * (int64_t)cout;

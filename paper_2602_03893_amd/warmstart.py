@@ -34,9 +34,12 @@ SIGMA_FULL = FULL.sigma          # 0.05 mm: the traces' kernel width
 SIGMA_HALF = HALF.sigma          # 0.1 mm on the half-resolution grid
 NOISE = 0.01
 LEVELS = 4
+# kappa of the half-resolution plan as measured when weights/unet4_c4.npy was
+# trained (power_kappa(), 30 iterations, seed 0)
+TRAINED_KAPPA = 0.0928654670715332
 
 
-def _phantom_job(seed):
+def phantom_sample(seed):
     """Host worker: the phantom and its 2 x 2 x 2 block-mean target."""
     x = I.vessel_phantom(FULL.grid, FULL.spacing, seed)
     nx, ny, nz = FULL.grid
@@ -108,7 +111,7 @@ def generate(problem, seeds, pool, log=print):
     T = torch.empty((n, d, h, w), dtype=torch.float32, device=problem.device)
     pos = {s: i for i, s in enumerate(seeds)}
     t0 = time.time()
-    for k, (seed, x, t) in enumerate(pool.imap_unordered(_phantom_job, seeds, chunksize=2)):
+    for k, (seed, x, t) in enumerate(pool.imap_unordered(phantom_sample, seeds, chunksize=2)):
         i = pos[seed]
         b = problem.traces(x, seed)
         problem.net_input(b, out=X[i].view(-1))
@@ -176,7 +179,7 @@ def evaluate(problem, net_params, seeds, max_iters=500, tol=1e-2, log=print):
     sig0 = SIGMA_FULL
     out = []
     for seed in seeds:
-        _, x, _ = _phantom_job(seed)
+        _, x, _ = phantom_sample(seed)
         b = problem.traces(x, seed)
         xt = torch.as_tensor(x).to(problem.device)
         norms = full.residual(full.forward(xt, problem.sig_full), b)
