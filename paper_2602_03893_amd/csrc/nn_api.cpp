@@ -48,21 +48,6 @@ hipStream_t hs(gpair_stream s) { return reinterpret_cast<hipStream_t>(s); }
 
 size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
 
-// Layout of a weight-gradient scratch buffer: split partials, then the
-// per-block channel sums of the bias gradient.
-struct WgradScratch {
-  int nsplit;
-  size_t wg_bytes, total;
-};
-
-WgradScratch wgrad_scratch(int64_t nvox_base, int taps, int cin, int cout) {
-  WgradScratch w;
-  w.nsplit = wgrad_splits(nvox_base, taps, cin, cout);
-  w.wg_bytes = round256((size_t)w.nsplit * taps * (cin == 1 ? 1 : cin) * cout * sizeof(float));
-  w.total = w.wg_bytes + round256((size_t)kSumBlocks * cout * sizeof(float));
-  return w;
-}
-
 }  // namespace
 
 extern "C" {
@@ -107,10 +92,10 @@ gpair_status gpair_nn_conv3(const gpair_nn_tensor *in, const void *w, const floa
 size_t gpair_nn_wgrad_partial_size(const gpair_nn_tensor *in, const gpair_nn_tensor *gout,
                                    int taps) {
   if (!in || !gout || (taps != 27 && taps != 8)) return 0;
-  const gpair_nn_tensor *base = taps == 27 ? gout : in;
-  const int64_t nvox = (int64_t)base->n * base->d * base->h * base->w;
-  if (nvox <= 0 || in->c < 1 || gout->c < 1) return 0;
-  return wgrad_scratch(nvox, taps, in->c, gout->c).total;
+  const gpair_nn_tensor *b = taps == 27 ? gout : in;
+  if (b->n < 1 || !pow2(b->d) || !pow2(b->h) || !pow2(b->w) || in->c < 1 || gout->c < 1)
+    return 0;
+  return wgrad_scratch_bytes(taps == 27 ? kConv3 : kUpDgrad, grid_of(b), in->c, gout->c);
 }
 
 gpair_status gpair_nn_conv3_wgrad(const gpair_nn_tensor *in, const gpair_nn_tensor *gout,
@@ -122,30 +107,16 @@ gpair_status gpair_nn_conv3_wgrad(const gpair_nn_tensor *in, const gpair_nn_tens
   if (cin == 1 && cout > 32) return GPAIR_ERR_INVALID_ARG;
   if (!view_ok(in, cin != 1) || !view_ok(gout) || !same_grid(in, gout))
     return GPAIR_ERR_INVALID_ARG;
-  const Grid g = grid_of(gout);
-  const WgradScratch sc = wgrad_scratch(g.nvox, 27, cin, cout);
-  hipError_t e;
-  if (cin == 1) {
-    e = launch_wgrad_c1(static_cast<const uint16_t *>(in->data), in->cs,
-                        static_cast<const uint16_t *>(gout->data), gout->cs, g, cout, partial,
-                        sc.nsplit, dw, hs(stream));
-  } else {
-    WgradArgs a{};
-    a.t_src = static_cast<const uint16_t *>(in->data);
-    a.t_cs = in->cs;
-    a.f_src = static_cast<const uint16_t *>(gout->data);
-    a.f_cs = gout->cs;
-    a.g = g;
-    a.partial = partial;
-    a.nsplit = sc.nsplit;
-    a.nchunks = (g.nvox + kChunk - 1) / kChunk;
-    e = launch_wgrad(a, kConv3, cin, cout, dw, hs(stream));
-  }
-  if (e != hipSuccess) return GPAIR_ERR_HIP;
-  if (db)
-    e = launch_chansum(static_cast<const uint16_t *>(gout->data), gout->cs, cout, g.nvox,
-                       partial + sc.wg_bytes / sizeof(float), db, hs(stream));
-  return hip_status(e);
+  WgradJob j;
+  j.mode = kConv3;
+  j.x = static_cast<const uint16_t *>(in->data);
+  j.x_cs = in->cs;
+  j.g = static_cast<const uint16_t *>(gout->data);
+  j.g_cs = gout->cs;
+  j.base = grid_of(gout);
+  j.cin = cin;
+  j.cout = cout;
+  return hip_status(launch_wgrad_job(j, partial, dw, db, hs(stream)));
 }
 
 gpair_status gpair_nn_maxpool2(const gpair_nn_tensor *in, const gpair_nn_tensor *out,
@@ -230,24 +201,16 @@ gpair_status gpair_nn_upconv2_wgrad(const gpair_nn_tensor *in, const gpair_nn_te
   if (!(cin == 32 || cin == 64 || cin == 128) || !(cout == 16 || cout == 32 || cout == 64))
     return GPAIR_ERR_INVALID_ARG;
   if (!half_grid(in, gout)) return GPAIR_ERR_INVALID_ARG;
-  const Grid g = grid_of(in);
-  const WgradScratch sc = wgrad_scratch(g.nvox, 8, cin, cout);
-  WgradArgs a{};
-  a.t_src = static_cast<const uint16_t *>(gout->data);
-  a.t_cs = gout->cs;
-  a.f_src = static_cast<const uint16_t *>(in->data);
-  a.f_cs = in->cs;
-  a.g = g;
-  a.partial = partial;
-  a.nsplit = sc.nsplit;
-  a.nchunks = (g.nvox + kChunk - 1) / kChunk;
-  hipError_t e = launch_wgrad(a, kUpDgrad, cin, cout, dw, hs(stream));
-  if (e != hipSuccess) return GPAIR_ERR_HIP;
-  if (db)
-    e = launch_chansum(static_cast<const uint16_t *>(gout->data), gout->cs, cout,
-                       grid_of(gout).nvox, partial + sc.wg_bytes / sizeof(float), db,
-                       hs(stream));
-  return hip_status(e);
+  WgradJob j;
+  j.mode = kUpDgrad;
+  j.x = static_cast<const uint16_t *>(in->data);
+  j.x_cs = in->cs;
+  j.g = static_cast<const uint16_t *>(gout->data);
+  j.g_cs = gout->cs;
+  j.base = grid_of(in);
+  j.cin = cin;
+  j.cout = cout;
+  return hip_status(launch_wgrad_job(j, partial, dw, db, hs(stream)));
 }
 
 gpair_status gpair_nn_head(const gpair_nn_tensor *in, const float *w, const float *b,

@@ -78,6 +78,23 @@ struct WgradArgs {
 // Split count of a weight-gradient launch (shared by the size query and the launch).
 int wgrad_splits(int64_t nvox, int taps, int cin, int cout);
 
+// A weight gradient (and optional bias gradient) of a 3x3x3 conv (mode kConv3:
+// x is the conv input, g the output gradient, both on `base`) or of the
+// stride-2 transposed conv (mode kUpDgrad: x on the coarse grid `base`, g on
+// the fine grid).
+struct WgradJob {
+  int mode;
+  const uint16_t *x;
+  int64_t x_cs;
+  const uint16_t *g;
+  int64_t g_cs;
+  Grid base;
+  int cin, cout;
+};
+size_t wgrad_scratch_bytes(int mode, const Grid &base, int cin, int cout);
+hipError_t launch_wgrad_job(const WgradJob &j, void *scratch, float *dw, float *db,
+                            hipStream_t s);
+
 hipError_t launch_conv3(const ConvArgs &a, int cin, int mode, hipStream_t s);
 hipError_t launch_conv_c1(const uint16_t *in, int64_t in_cs, const Grid &g, const uint16_t *w,
                           const float *bias, uint16_t *out, int64_t out_cs, int cout, int epi,

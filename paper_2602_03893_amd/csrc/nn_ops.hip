@@ -504,6 +504,251 @@ __global__ __launch_bounds__(kConvBlock) void wgrad_c1_kernel(const uint16_t *__
   }
 }
 
+// ---------------------------------------------------------------------------
+// Streamed weight gradients (grid rows of at least 8 voxels).  The operands
+// are first rewritten in 8-voxel blocks, [voxel / 8][channel][8] (bfloat16),
+// the conv input as three copies shifted by dx = -1, 0, +1 inside each row
+// (zero outside), the transposed conv's output gradient split by child tap
+// ([tap][coarse voxel / 8][channel][8]).  Every A / B fragment of the
+// weight-gradient GEMM (K = voxels) is then one aligned 16-byte load of 8
+// consecutive voxels of one channel, and the 64 lanes of a fragment read one
+// contiguous 1 KiB block (16 channels x 32 voxels): a (dz, dy) shift moves
+// whole 8-voxel blocks, a dx shift picks the copy.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t half_of(const u32x4 &q, int c) {
+  const uint32_t w = q[c >> 1];
+  return (c & 1) ? (w >> 16) : (w & 0xffffu);
+}
+
+// One 8-voxel group x 8 channels: out[c][j] = vox[j][c] for j < 8.
+__device__ __forceinline__ u32x4 column(const u32x4 *vox, int c) {
+  u32x4 o;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) o[k] = half_of(vox[2 * k], c) | (half_of(vox[2 * k + 1], c) << 16);
+  return o;
+}
+
+// xt[s][v / 8][c][v % 8] = x[v + s - 1][c] (0 where x + s - 1 leaves the row).
+__global__ __launch_bounds__(256) void xt_shift3_kernel(const uint16_t *__restrict__ x,
+                                                        int64_t cs, int C, Grid g,
+                                                        uint16_t *__restrict__ xt) {
+  const int oct = C / 8;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (g.nvox / 8) * oct) return;
+  const int64_t v0 = (idx / oct) * 8;
+  const int oc = (int)(idx % oct);
+  const int x0 = (int)(v0 & ((1 << g.lw) - 1));
+  u32x4 q[10];
+  q[0] = x0 > 0 ? ld16(x + (v0 - 1) * cs + 8 * oc) : zero4();
+#pragma unroll
+  for (int j = 0; j < 8; ++j) q[j + 1] = ld16(x + (v0 + j) * cs + 8 * oc);
+  q[9] = x0 + 8 < (1 << g.lw) ? ld16(x + (v0 + 8) * cs + 8 * oc) : zero4();
+#pragma unroll
+  for (int sh = 0; sh < 3; ++sh)
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      *reinterpret_cast<u32x4 *>(xt + (int64_t)sh * C * g.nvox + (v0 / 8 * C + 8 * oc + c) * 8) =
+          column(q + sh, c);
+}
+
+// Block-level channel sums of an 8 x 8 tile per thread: partial[block][C].
+__device__ __forceinline__ void block_chan_sums(const u32x4 *vox, bool live, int C,
+                                                float *__restrict__ partial) {
+  __shared__ float sh[256][8];
+  const int oct = C / 8;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    float t = 0.f;
+    if (live)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) t += bf2f(half_of(vox[j], c));
+    sh[threadIdx.x][c] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < C) {
+    const int oc = threadIdx.x / 8, c = threadIdx.x % 8;
+    float t = 0.f;
+    for (int k = oc; k < 256; k += oct) t += sh[k][c];
+    partial[(int64_t)blockIdx.x * C + threadIdx.x] = t;
+  }
+}
+
+// xt[v / 8][c][v % 8] = x[v][c]; optional per-block channel sums.
+__global__ __launch_bounds__(256) void xt_plain_kernel(const uint16_t *__restrict__ x,
+                                                       int64_t cs, int C, int64_t V,
+                                                       uint16_t *__restrict__ xt,
+                                                       float *__restrict__ sums) {
+  const int oct = C / 8;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool live = idx < (V / 8) * oct;
+  const int64_t v0 = (idx / oct) * 8;
+  const int oc = (int)(idx % oct);
+  u32x4 q[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) q[j] = live ? ld16(x + (v0 + j) * cs + 8 * oc) : zero4();
+  if (live)
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      *reinterpret_cast<u32x4 *>(xt + (v0 / 8 * C + 8 * oc + c) * 8) = column(q, c);
+  if (sums) block_chan_sums(q, live, C, sums);
+}
+
+// gt[t][v / 8][c][v % 8] = g[child(v, t)][c] for coarse voxel v; optional sums.
+__global__ __launch_bounds__(256) void gt_s2d_kernel(const uint16_t *__restrict__ gf,
+                                                     int64_t cs, int C, Grid cg,
+                                                     uint16_t *__restrict__ gt,
+                                                     float *__restrict__ sums) {
+  const int oct = C / 8;
+  const int64_t per_tap = (cg.nvox / 8) * oct;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool live = idx < 8 * per_tap;
+  const int t = (int)(idx / per_tap);
+  const int64_t rem = idx % per_tap;
+  const int64_t v0 = (rem / oct) * 8;
+  const int oc = (int)(rem % oct);
+  const int ld = cg.ld, lh = cg.lh, lw = cg.lw;
+  u32x4 q[8];
+  if (live) {
+    const int x0 = (int)(v0 & ((1 << lw) - 1)), y = (int)((v0 >> lw) & ((1 << lh) - 1)),
+              z = (int)((v0 >> (lw + lh)) & ((1 << ld) - 1));
+    const int64_t n = v0 >> (lw + lh + ld);
+    const int tz = t >> 2, ty = (t >> 1) & 1, tx = t & 1;
+    const int64_t f0 =
+        ((((n << (ld + 1)) + 2 * z + tz) << (lh + 1)) + 2 * y + ty) * ((int64_t)2 << lw) +
+        2 * x0 + tx;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) q[j] = ld16(gf + (f0 + 2 * j) * cs + 8 * oc);
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      *reinterpret_cast<u32x4 *>(gt + (int64_t)t * C * cg.nvox + (v0 / 8 * C + 8 * oc + c) * 8) =
+          column(q, c);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) q[j] = zero4();
+  }
+  if (sums) block_chan_sums(q, live, C, sums);
+}
+
+struct StreamArgs {
+  const uint16_t *xt;  // conv3: [3][V/8][CI][8]; transposed conv: [V/8][CI][8]
+  const uint16_t *gt;  // conv3: [V/8][CO][8];    transposed conv: [8][V/8][CO][8]
+  Grid g;              // base grid (coarse for the transposed conv)
+  int CI, CO, taps, nt, mgroups;
+  int64_t kvox;        // voxels per split, multiple of 32
+  float *partial;      // [nsplit][taps][CI][CO]
+};
+
+// One wave: taps [t0, t0 + nt) x NM input-channel blocks x NN output-channel
+// blocks, summed over the split's voxels.  D[ci][co] += A[ci][v] B[v][co].
+template <int NTM, int NM, int NN, int MODE>
+__global__ __launch_bounds__(64) void wgrad_stream_kernel(StreamArgs a) {
+  const int lane = threadIdx.x;
+  const int r = lane & 15, q = lane >> 4;
+  const int split = blockIdx.x;
+  const int tg = blockIdx.y / a.mgroups, mg = blockIdx.y % a.mgroups;
+  const int t0 = tg * a.nt;
+  const int ntap = min(a.nt, a.taps - t0);
+  const int ci0 = mg * NM * 16;
+  const int64_t V = a.g.nvox;
+  const int64_t vb = (int64_t)split * a.kvox;
+  const int64_t ve = min(V, vb + a.kvox);
+  const int ld = a.g.ld, lh = a.g.lh, lw = a.g.lw;
+  const int D = 1 << ld, H = 1 << lh;
+  f32x4 acc[NTM][NM][NN];
+#pragma unroll
+  for (int i = 0; i < NTM; ++i)
+#pragma unroll
+    for (int m = 0; m < NM; ++m)
+#pragma unroll
+      for (int n = 0; n < NN; ++n) acc[i][m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // per-tap element offsets: conv3, the dx copy plus the (dz, dy) shift in
+  // whole 8-voxel blocks; transposed conv, the plane of child tap t
+  int64_t aoff[NTM];
+  int dzs[NTM], dys[NTM];
+#pragma unroll
+  for (int i = 0; i < NTM; ++i) {
+    const int t = t0 + (i < ntap ? i : 0);
+    if (MODE == kConv3) {
+      const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+      dzs[i] = dz;
+      dys[i] = dy;
+      const int64_t shift = ((int64_t)dz << (lh + lw)) + ((int64_t)dy << lw);  // multiple of 8
+      aoff[i] = (int64_t)(dx + 1) * a.CI * V + shift * a.CI;
+    } else {
+      dzs[i] = dys[i] = 0;
+      aoff[i] = (int64_t)t * a.CO * V;
+    }
+  }
+  for (int64_t v0 = vb; v0 < ve; v0 += 32) {
+    const int64_t v = v0 + 8 * q;  // this lane group's 8 voxels (one row segment)
+    const bool vok = v < ve;
+    const int y = (int)((v >> lw) & (H - 1)), z = (int)((v >> (lw + lh)) & (D - 1));
+    if (MODE == kConv3) {
+      const int64_t bo = (v >> 3) * a.CO * 8;
+      const int64_t ao = (v >> 3) * a.CI * 8;
+      u32x4 bf[NN];
+#pragma unroll
+      for (int n = 0; n < NN; ++n) bf[n] = vok ? ld16(a.gt + bo + (16 * n + r) * 8) : zero4();
+#pragma unroll
+      for (int i = 0; i < NTM; ++i) {
+        if (i < ntap) {
+          const bool ok = vok && (unsigned)(z + dzs[i]) < (unsigned)D &&
+                          (unsigned)(y + dys[i]) < (unsigned)H;
+#pragma unroll
+          for (int m = 0; m < NM; ++m) {
+            const u32x4 af = ok ? ld16(a.xt + aoff[i] + ao + (ci0 + 16 * m + r) * 8) : zero4();
+#pragma unroll
+            for (int n = 0; n < NN; ++n) acc[i][m][n] = mfma16(af, bf[n], acc[i][m][n]);
+          }
+        }
+      }
+    } else {
+      const int64_t ao = (v >> 3) * a.CI * 8;
+      const int64_t bo = (v >> 3) * a.CO * 8;
+      u32x4 af[NM];
+#pragma unroll
+      for (int m = 0; m < NM; ++m) af[m] = vok ? ld16(a.xt + ao + (ci0 + 16 * m + r) * 8) : zero4();
+#pragma unroll
+      for (int i = 0; i < NTM; ++i) {
+        if (i < ntap) {
+#pragma unroll
+          for (int n = 0; n < NN; ++n) {
+            const u32x4 bf = vok ? ld16(a.gt + aoff[i] + bo + (16 * n + r) * 8) : zero4();
+#pragma unroll
+            for (int m = 0; m < NM; ++m) acc[i][m][n] = mfma16(af[m], bf, acc[i][m][n]);
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NTM; ++i) {
+    if (i < ntap) {
+      float *dst = a.partial + ((int64_t)split * a.taps + t0 + i) * a.CI * a.CO;
+#pragma unroll
+      for (int m = 0; m < NM; ++m)
+#pragma unroll
+        for (int n = 0; n < NN; ++n)
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            dst[(int64_t)(ci0 + 16 * m + 4 * q + k) * a.CO + 16 * n + r] = acc[i][m][n][k];
+    }
+  }
+}
+
+// red[gi][e] = sum over splits s in [64 gi, 64 gi + 64) of partial[s][e].
+__global__ __launch_bounds__(256) void reduce_stage1_kernel(const float *__restrict__ partial,
+                                                            int nsplit, int64_t n,
+                                                            float *__restrict__ red) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const int s0 = blockIdx.y * 64;
+  const int s1 = min(nsplit, s0 + 64);
+  float s = 0.f;
+  for (int k = s0; k < s1; ++k) s += partial[(int64_t)k * n + e];
+  red[(int64_t)blockIdx.y * n + e] = s;
+}
+
 // out[e] = sum_s partial[s][e], s ascending.
 __global__ __launch_bounds__(256) void reduce_splits_kernel(const float *__restrict__ partial,
                                                             int nsplit, int64_t n,
@@ -1038,6 +1283,213 @@ hipError_t launch_upsample2(const float *x, int n, int d, int h, int w, float *o
   const int64_t tot = (int64_t)n * 8 * d * h * w;
   upsample2_kernel<<<blocks_for(tot, 256), 256, 0, s>>>(x, n, d, h, w, out);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Weight-gradient jobs: path choice, scratch layout, launches.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct StreamCfg {
+  int ntm, nm, nn;  // template shape
+  int nt, mgroups, tgroups;
+};
+
+// Tiles per wave (taps x input-channel blocks x output-channel blocks) are
+// kept to at most 16 (64 accumulator registers) so that several waves per SIMD
+// hide the load latency of the streamed operands.
+StreamCfg stream_cfg(int taps, int cin, int cout) {
+  StreamCfg c;
+  const int tpt = (cin / 16) * (cout / 16);
+  c.nn = cout / 16;
+  c.nm = cin / 16;
+  c.mgroups = 1;
+  if (tpt <= 16) {
+    if (taps == 27)
+      c.ntm = tpt == 1 ? 9 : tpt == 2 ? 7 : tpt == 4 ? 4 : tpt == 8 ? 2 : 1;
+    else
+      c.ntm = tpt <= 2 ? 8 : tpt == 4 ? 4 : tpt == 8 ? 2 : 1;
+  } else {
+    c.ntm = 1;
+    c.nm = 16 / c.nn;
+    c.mgroups = (cin / 16) / c.nm;
+  }
+  c.nt = c.ntm < taps ? c.ntm : taps;
+  c.tgroups = (taps + c.nt - 1) / c.nt;
+  return c;
+}
+
+enum WgradPath { kPathC1, kPathStaged, kPathStream };
+
+struct WgradLayout {
+  int path, nsplit, g2, nblk_sum, g2sum;
+  int64_t kvox;
+  size_t partial, red2, xt, gt, sums, sums2, total;
+};
+
+// base: the conv grid (conv3) or the coarse grid (transposed conv).
+WgradLayout wgrad_layout(int mode, const Grid &base, int cin, int cout) {
+  WgradLayout L{};
+  const int taps = mode == kConv3 ? 27 : 8;
+  const int64_t V = base.nvox;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t o = off;
+    off += (b + 255) & ~size_t(255);
+    return o;
+  };
+  if (mode == kConv3 && cin == 1) {
+    L.path = kPathC1;
+  } else if (base.lw >= 3) {
+    L.path = kPathStream;
+  } else {
+    L.path = kPathStaged;
+  }
+  const int64_t n = (int64_t)taps * (cin == 1 ? 1 : cin) * cout;
+  if (L.path == kPathStream) {
+    const StreamCfg c = stream_cfg(taps, cin, cout);
+    const int groups = c.tgroups * c.mgroups;
+    int64_t ns = (4096 + groups - 1) / groups;
+    const int64_t budget = (int64_t)(kWgradPartialCap / ((size_t)n * 4));
+    if (ns > budget) ns = budget;
+    int64_t kv = (V + ns - 1) / ns;
+    if (kv < 256) kv = 256;
+    kv = (kv + 31) / 32 * 32;
+    L.kvox = kv;
+    L.nsplit = (int)((V + kv - 1) / kv);
+    L.g2 = (L.nsplit + 63) / 64;
+    L.partial = take((size_t)L.nsplit * n * 4);
+    L.red2 = take((size_t)L.g2 * n * 4);
+    const int64_t vfine_or_same = mode == kConv3 ? V : 8 * V;
+    L.xt = take((size_t)(mode == kConv3 ? 3 : 1) * cin * V * 2);
+    L.gt = take((size_t)cout * vfine_or_same * 2);
+    const int64_t threads = (vfine_or_same / 8) * (cout / 8);
+    L.nblk_sum = (int)((threads + 255) / 256);
+  } else {
+    L.nsplit = wgrad_splits(V, taps, cin, cout);
+    L.partial = take((size_t)L.nsplit * n * 4);
+    L.g2 = 0;
+    L.nblk_sum = kSumBlocks;
+  }
+  L.g2sum = (L.nblk_sum + 63) / 64;
+  L.sums = take((size_t)L.nblk_sum * cout * 4);
+  L.sums2 = take((size_t)L.g2sum * cout * 4);
+  L.total = off;
+  return L;
+}
+
+// out[e] = sum over s < ns of partial[s][e], in a fixed order (two stages when
+// there are many splits).
+hipError_t reduce_fixed(const float *partial, int ns, int64_t n, float *red2, float *out,
+                        hipStream_t s) {
+  if (ns <= 64 || !red2) {
+    reduce_splits_kernel<<<blocks_for(n, 256), 256, 0, s>>>(partial, ns, n, out);
+    return hipGetLastError();
+  }
+  const int g2 = (ns + 63) / 64;
+  reduce_stage1_kernel<<<dim3(blocks_for(n, 256), g2), 256, 0, s>>>(partial, ns, n, red2);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  reduce_splits_kernel<<<blocks_for(n, 256), 256, 0, s>>>(red2, g2, n, out);
+  return hipGetLastError();
+}
+
+template <int NTM, int NM, int NN, int MODE>
+hipError_t stream_go(const StreamArgs &a, int nsplit, int groups, hipStream_t s) {
+  wgrad_stream_kernel<NTM, NM, NN, MODE><<<dim3((unsigned)nsplit, (unsigned)groups), 64, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t stream_dispatch(const StreamCfg &c, const StreamArgs &a, int nsplit, hipStream_t s) {
+  const int groups = c.tgroups * c.mgroups;
+#define GPAIR_SW(T, M, N) \
+  if (c.ntm == T && c.nm == M && c.nn == N) return stream_go<T, M, N, MODE>(a, nsplit, groups, s);
+  GPAIR_SW(9, 1, 1) GPAIR_SW(7, 2, 1) GPAIR_SW(7, 1, 2) GPAIR_SW(4, 2, 2) GPAIR_SW(4, 4, 1)
+  GPAIR_SW(4, 1, 4) GPAIR_SW(2, 4, 2) GPAIR_SW(2, 2, 4) GPAIR_SW(2, 8, 1) GPAIR_SW(2, 1, 8)
+  GPAIR_SW(1, 4, 4) GPAIR_SW(1, 8, 2) GPAIR_SW(1, 2, 8) GPAIR_SW(8, 2, 1)
+#undef GPAIR_SW
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+size_t wgrad_scratch_bytes(int mode, const Grid &base, int cin, int cout) {
+  return wgrad_layout(mode, base, cin, cout).total;
+}
+
+hipError_t launch_wgrad_job(const WgradJob &j, void *scratch, float *dw, float *db,
+                            hipStream_t s) {
+  const WgradLayout L = wgrad_layout(j.mode, j.base, j.cin, j.cout);
+  char *base = static_cast<char *>(scratch);
+  float *partial = reinterpret_cast<float *>(base + L.partial);
+  const int taps = j.mode == kConv3 ? 27 : 8;
+  const int64_t n = (int64_t)taps * (j.cin == 1 ? 1 : j.cin) * j.cout;
+  hipError_t e;
+  if (L.path == kPathC1) {
+    e = launch_wgrad_c1(j.x, j.x_cs, j.g, j.g_cs, j.base, j.cout, partial, L.nsplit, dw, s);
+    if (e != hipSuccess) return e;
+  } else if (L.path == kPathStaged) {
+    WgradArgs a{};
+    if (j.mode == kConv3) {
+      a.t_src = j.x;
+      a.t_cs = j.x_cs;
+      a.f_src = j.g;
+      a.f_cs = j.g_cs;
+    } else {
+      a.t_src = j.g;
+      a.t_cs = j.g_cs;
+      a.f_src = j.x;
+      a.f_cs = j.x_cs;
+    }
+    a.g = j.base;
+    a.partial = partial;
+    a.nsplit = L.nsplit;
+    a.nchunks = (j.base.nvox + kChunk - 1) / kChunk;
+    e = launch_wgrad(a, j.mode, j.cin, j.cout, dw, s);
+    if (e != hipSuccess) return e;
+  } else {
+    uint16_t *xt = reinterpret_cast<uint16_t *>(base + L.xt);
+    uint16_t *gt = reinterpret_cast<uint16_t *>(base + L.gt);
+    float *sums = db ? reinterpret_cast<float *>(base + L.sums) : nullptr;
+    const int64_t V = j.base.nvox;
+    if (j.mode == kConv3) {
+      xt_shift3_kernel<<<blocks_for((V / 8) * (j.cin / 8), 256), 256, 0, s>>>(j.x, j.x_cs, j.cin,
+                                                                              j.base, xt);
+      xt_plain_kernel<<<L.nblk_sum, 256, 0, s>>>(j.g, j.g_cs, j.cout, V, gt, sums);
+    } else {
+      xt_plain_kernel<<<blocks_for((V / 8) * (j.cin / 8), 256), 256, 0, s>>>(j.x, j.x_cs, j.cin,
+                                                                             V, xt, nullptr);
+      gt_s2d_kernel<<<L.nblk_sum, 256, 0, s>>>(j.g, j.g_cs, j.cout, j.base, gt, sums);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const StreamCfg c = stream_cfg(taps, j.cin, j.cout);
+    StreamArgs a;
+    a.xt = xt;
+    a.gt = gt;
+    a.g = j.base;
+    a.CI = j.cin;
+    a.CO = j.cout;
+    a.taps = taps;
+    a.nt = c.nt;
+    a.mgroups = c.mgroups;
+    a.kvox = L.kvox;
+    a.partial = partial;
+    e = j.mode == kConv3 ? stream_dispatch<kConv3>(c, a, L.nsplit, s)
+                         : stream_dispatch<kUpDgrad>(c, a, L.nsplit, s);
+    if (e != hipSuccess) return e;
+    e = reduce_fixed(partial, L.nsplit, n, reinterpret_cast<float *>(base + L.red2), dw, s);
+    if (e != hipSuccess) return e;
+    if (db)
+      return reduce_fixed(sums, L.nblk_sum, j.cout, reinterpret_cast<float *>(base + L.sums2),
+                          db, s);
+    return hipSuccess;
+  }
+  if (!db) return hipSuccess;
+  // bias gradient of the other paths: channel sums of the output gradient
+  const int64_t nv = j.mode == kConv3 ? j.base.nvox : 8 * j.base.nvox;
+  return launch_chansum(j.g, j.g_cs, j.cout, nv, reinterpret_cast<float *>(base + L.sums), db, s);
 }
 
 }  // namespace nn

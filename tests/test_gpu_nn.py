@@ -165,7 +165,8 @@ def test_conv3_dgrad_with_relu_mask(n, d, h, w, cin, cout):
 @pytest.mark.parametrize("n,d,h,w,cin,cout", [(2, 4, 8, 16, 16, 16), (1, 8, 8, 8, 32, 16),
                                               (1, 4, 8, 8, 16, 32), (1, 4, 4, 8, 64, 64),
                                               (1, 2, 4, 8, 128, 64), (1, 2, 4, 4, 128, 128),
-                                              (1, 1, 2, 8, 32, 32), (2, 8, 8, 8, 1, 16)])
+                                              (1, 1, 2, 8, 32, 32), (2, 8, 8, 8, 1, 16),
+                                              (2, 16, 32, 32, 16, 16), (1, 8, 32, 64, 32, 16)])
 def test_conv3_wgrad(n, d, h, w, cin, cout):
     m = nn()
     _say(f"case: conv3 wgrad {cin}x{cout} on {n}x{d}x{h}x{w}")
@@ -205,7 +206,10 @@ def test_maxpool_forward_backward_with_ties():
 
 
 @pytest.mark.parametrize("n,d,h,w,cin,cout", [(2, 2, 4, 8, 32, 16), (1, 4, 4, 4, 64, 32),
-                                              (1, 2, 2, 4, 128, 64), (1, 1, 2, 2, 64, 32)])
+                                              (1, 2, 2, 4, 128, 64), (1, 1, 2, 2, 64, 32),
+                                              (2, 8, 16, 16, 32, 16), (1, 4, 8, 16, 64, 32),
+                                              (1, 2, 8, 8, 128, 64), (1, 2, 4, 8, 32, 32),
+                                              (1, 2, 8, 8, 128, 32), (1, 2, 4, 8, 64, 64)])
 def test_upconv_forward_dgrad_wgrad(n, d, h, w, cin, cout):
     m = nn()
     _say(f"case: upconv {cin}->{cout} on coarse {n}x{d}x{h}x{w}")
