@@ -191,25 +191,28 @@ struct FwdLoop {
 };
 
 // The kernel loop of one wave over its tile when every kernel of the tile
-// has NT - 2 .. NT taps.  Two records are in flight in alternating registers
-// (no copies), and the tap count needs no per-kernel dispatch.
+// has NT - 2 .. NT taps.  Kernels go in pairs: both pair stages sit in one
+// straight-line block, so their float64 chains interleave, and the records of
+// the next pair are fetched meanwhile (clamped to the tile's last record).
 template <int NT>
 __device__ __forceinline__ void kernel_loop(const FwdLoop &c, float *col, int k0, int kend) {
-  KernelRec ra = c.krec[k0], rb;
-  for (int k = k0; k < kend; k += 2) {
-    if (k + 1 < kend) rb = c.krec[k + 1];
-    {
-      const Taps t = pair_taps(c.s, ra, c.nb, c.omax, c.inv_vdt, c.t0_over_dt, c.vdt);
-      taps_rmw<NT>(col + t.o * kWave, t.f, t.q, t.d, ra.rq, c.vdt_f,
-                   ra.ntap - (t.last_ok ? 0 : 1));
-    }
-    if (k + 1 >= kend) break;
-    if (k + 2 < kend) ra = c.krec[k + 2];
-    {
-      const Taps t = pair_taps(c.s, rb, c.nb, c.omax, c.inv_vdt, c.t0_over_dt, c.vdt);
-      taps_rmw<NT>(col + t.o * kWave, t.f, t.q, t.d, rb.rq, c.vdt_f,
-                   rb.ntap - (t.last_ok ? 0 : 1));
-    }
+  const int last = kend - 1;
+  const int pend = k0 + ((kend - k0) & ~1);
+  KernelRec ra = c.krec[k0], rb = c.krec[min(k0 + 1, last)];
+  for (int k = k0; k < pend; k += 2) {
+    const Taps ta = pair_taps(c.s, ra, c.nb, c.omax, c.inv_vdt, c.t0_over_dt, c.vdt);
+    const Taps tb = pair_taps(c.s, rb, c.nb, c.omax, c.inv_vdt, c.t0_over_dt, c.vdt);
+    const float rqa = ra.rq, rqb = rb.rq;
+    const int nva = ra.ntap - (ta.last_ok ? 0 : 1), nvb = rb.ntap - (tb.last_ok ? 0 : 1);
+    ra = c.krec[min(k + 2, last)];
+    rb = c.krec[min(k + 3, last)];
+    taps_rmw<NT>(col + ta.o * kWave, ta.f, ta.q, ta.d, rqa, c.vdt_f, nva);
+    taps_rmw<NT>(col + tb.o * kWave, tb.f, tb.q, tb.d, rqb, c.vdt_f, nvb);
+  }
+  if (pend < kend) {
+    const Taps t = pair_taps(c.s, ra, c.nb, c.omax, c.inv_vdt, c.t0_over_dt, c.vdt);
+    taps_rmw<NT>(col + t.o * kWave, t.f, t.q, t.d, ra.rq, c.vdt_f,
+                 ra.ntap - (t.last_ok ? 0 : 1));
   }
 }
 
@@ -297,6 +300,26 @@ __global__ __launch_bounds__(WAVES * kWave) void forward_kernel(
   // consecutive lanes add to consecutive addresses of y (coalesced float
   // atomics; per-lane rows would scatter one atomic per cache line, which
   // measured twice as slow with dense amplitudes).
+  if (a.L <= kWave) {
+    // One sample per lane: rows in groups of 8, all reads before the adds.
+    const bool in_seg = lane < a.L;
+    for (int row0 = 0; row0 < kWave; row0 += 8) {
+      float v[8];
+      int n[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        v[u] = in_seg ? seg[lane * kWave + row0 + u] : 0.0f;
+        n[u] = __builtin_amdgcn_readlane(nb, row0 + u) + lane;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int jr = sg * kWave + row0 + u;
+        if (jr < a.Nd && n[u] >= 0 && n[u] < a.Nt && v[u] != 0.0f)
+          unsafeAtomicAdd(a.y + (int64_t)jr * a.Nt + n[u], v[u]);
+      }
+    }
+    return;
+  }
   for (int row = 0; row < kWave; ++row) {
     const int jr = sg * kWave + row;
     if (jr >= a.Nd) break;
