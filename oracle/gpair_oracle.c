@@ -160,3 +160,86 @@ int oracle_num_threads(void) {
   return 1;
 #endif
 }
+
+/*
+ * ASSA operators (Methods, "Adaptive supersampling alignment"), written per
+ * kernel-sensor pair: the composition of the projection onto the upsampled
+ * grid, the transposed convolution with h and the decimation contributes,
+ * for a pair with snapped index k = floor((r/v - t0) f_up + 0.5) on the
+ * alpha-times finer grid, amp/r * h[alpha n - k] to every sample n with
+ * |alpha n - k| <= K.  The adjoint is the transpose of the same sum.
+ *   h[k] = 0.5 * d * exp(-d^2 / (2 sigma^2)),  d = -v k dt / alpha.
+ * Pairs whose snapped index lies outside [0, alpha nt) contribute nothing
+ * (the impulse grid has alpha nt points).
+ */
+static int64_t floor_div(int64_t a, int64_t b) {  /* b > 0 */
+  int64_t q = a / b;
+  if ((a % b) != 0 && a < 0) --q;
+  return q;
+}
+
+static double *assa_kernel(double dt, double v, double sigma, int64_t alpha, int64_t K) {
+  double *h = (double *)malloc(sizeof(double) * (size_t)(2 * K + 1));
+  for (int64_t k = -K; k <= K; ++k) {
+    double d = -v * (double)k * (dt / (double)alpha);
+    h[k + K] = 0.5 * d * exp(-(d * d) / (2.0 * sigma * sigma));
+  }
+  return h;
+}
+
+static int64_t assa_index(double r, double v, double t0, double f_up) {
+  return (int64_t)floor((r / v - t0) * f_up + 0.5);
+}
+
+void oracle_assa_forward(int64_t m, const float *cx, const float *cy, const float *cz,
+                         const double *amp, int64_t nd, const float *sens, int64_t nt,
+                         double dt, double t0, double v, double sigma, int64_t alpha,
+                         int64_t K, double *y) {
+  double *h = assa_kernel(dt, v, sigma, alpha, K);
+  const double f_up = (double)alpha / dt;
+  const int64_t ntu = alpha * nt;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t j = 0; j < nd; ++j) {
+    double *yj = y + j * nt;
+    for (int64_t n = 0; n < nt; ++n) yj[n] = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+      const double r = pair_distance(sens + 3 * j, cx[i], cy[i], cz[i]);
+      const int64_t k = assa_index(r, v, t0, f_up);
+      if (k < 0 || k >= ntu) continue;
+      const double w = amp[i] / r;
+      int64_t lo = -floor_div(-(k - K), alpha);  /* ceil((k - K) / alpha) */
+      int64_t hi = floor_div(k + K, alpha);
+      if (lo < 0) lo = 0;
+      if (hi > nt - 1) hi = nt - 1;
+      for (int64_t n = lo; n <= hi; ++n) yj[n] += w * h[alpha * n - k + K];
+    }
+  }
+  free(h);
+}
+
+void oracle_assa_adjoint(int64_t m, const float *cx, const float *cy, const float *cz,
+                         int64_t nd, const float *sens, int64_t nt, double dt, double t0,
+                         double v, double sigma, int64_t alpha, int64_t K,
+                         const double *delta, double *g) {
+  double *h = assa_kernel(dt, v, sigma, alpha, K);
+  const double f_up = (double)alpha / dt;
+  const int64_t ntu = alpha * nt;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < m; ++i) {
+    double acc = 0.0;
+    for (int64_t j = 0; j < nd; ++j) {
+      const double r = pair_distance(sens + 3 * j, cx[i], cy[i], cz[i]);
+      const int64_t k = assa_index(r, v, t0, f_up);
+      if (k < 0 || k >= ntu) continue;
+      int64_t lo = -floor_div(-(k - K), alpha);
+      int64_t hi = floor_div(k + K, alpha);
+      if (lo < 0) lo = 0;
+      if (hi > nt - 1) hi = nt - 1;
+      double s = 0.0;
+      for (int64_t n = lo; n <= hi; ++n) s += h[alpha * n - k + K] * delta[j * nt + n];
+      acc += s / r;
+    }
+    g[i] = acc;
+  }
+  free(h);
+}
