@@ -376,11 +376,95 @@ gpair_status gpair_solve(gpair_plan p, const float *b, float *A, float *sigma,
                          gpair_stream stream);
 
 /* ------------------------------------------------------------------------ */
+/* f1. ASSA operators (adaptive supersampling alignment)                      */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * The paper's own discretisation of the forward model (Methods, "Adaptive
+ * supersampling alignment for the differentiable model operator", and its
+ * Algorithm for the forward and adjoint operators): one kernel width sigma
+ * shared by all kernels, times of flight snapped to an alpha-times finer time
+ * grid, one shared convolution kernel h, decimation back to the sampling grid.
+ * It approximates gpair_forward with a constant sigma (the snapping moves each
+ * pulse by at most half a fine step); it is not bit-identical to it.
+ *
+ * Grid ("Adaptive Grid Parameters" equation), with the window n_sigma of the
+ * plan as the "3" of the paper:
+ *   n_half = ceil(n_sigma sigma / (v dt))   (taken with a relative tolerance
+ *            of 1e-9, so that exact integers are not pushed up by rounding)
+ *   alpha  = max(1, ceil(12 / n_half))      (N_min = 25 taps at least)
+ *   K      = alpha * n_half,  fine step dt_up = dt / alpha,
+ *   fine grid of n_fine = alpha * n_samples points, point k at t0 + k dt_up.
+ */
+typedef struct gpair_assa_grid {
+  int32_t n_half; /* kernel half-width in samples                       */
+  int32_t alpha;  /* upsampling factor                                  */
+  int32_t K;      /* kernel half-width in fine samples (alpha * n_half) */
+  int32_t n_fine; /* alpha * n_samples                                  */
+  int32_t fwd_segment; /* fine samples per forward LDS segment          */
+  int32_t fwd_passes;  /* passes of the forward over a tile's time shell
+                          (1 unless the shell exceeds the LDS budget)   */
+  int32_t adj_segment; /* fine samples per adjoint LDS stage row        */
+  int32_t adj_stage_sensors; /* sensors staged per adjoint LDS refill   */
+} gpair_assa_grid;
+
+/*
+ * Grid parameters and segment sizes for `sigma`.  sigma must be finite and in
+ * (0, sigma_max] of the plan (the far-field check of the plan assumes it).
+ * Errors: SIGMA_RANGE; INVALID_ARG when K > 120 (n_half > 120) or the fine
+ * indices of the geometry exceed 1e9.
+ */
+gpair_status gpair_assa_grid_params(gpair_plan p, double sigma, gpair_assa_grid *out);
+
+/*
+ * Bytes of the device work buffer gpair_assa_adjoint needs for `sigma`
+ * (the convolved residual, float32 [n_sensors][alpha n_samples]).
+ * Errors: as gpair_assa_grid_params.
+ */
+gpair_status gpair_assa_workspace_size(gpair_plan p, double sigma, size_t *bytes);
+
+/*
+ * y = S(h * P_up(x)):
+ *   P_up: for each kernel-sensor pair, k_ij = floor((r_ij / v - t0) alpha/dt
+ *         + 1/2) (float64), and x_i / r_ij is added to z_j[k_ij]; pairs with
+ *         k_ij outside [0, n_fine) are dropped;
+ *   h:    h[m] = (1/2) d exp(-d^2 / (2 sigma^2)), d = -v m dt_up, m = -K..K
+ *         (normalisation 1/2: a pulse whose time of flight is on the fine
+ *         grid gives exactly the samples of Eq. (single_forward));
+ *   S:    y_j[n] = (h * z_j)[alpha n], n in [0, n_samples).
+ *  x      device float32 [n_kernels], any sign.
+ *  sigma  the shared kernel width (m).
+ *  y      device float32 [n_sensors][n_samples], overwritten.
+ * Impulses accumulate in float32 (LDS), h and the convolution are float32.
+ * Errors: INVALID_ARG, SIGMA_RANGE, HIP.
+ */
+gpair_status gpair_assa_forward(gpair_plan p, const float *x, double sigma, float *y,
+                                gpair_stream stream);
+
+/*
+ * The exact transpose of gpair_assa_forward (the "Adjoint Operator"
+ * subsection): zero-filling delta onto the fine grid, correlation with h
+ * (convolution with the reversed kernel), back-projection
+ *   g_i = sum_j delta_conv_j[k_ij] / r_ij      (pairs with k_ij in range).
+ *  delta  device float32 [n_sensors][n_samples].
+ *  g      device float32 [n_kernels], overwritten.
+ *  work   device buffer of at least gpair_assa_workspace_size bytes, owned by
+ *         the caller, 256-byte aligned; its contents are scratch.
+ * Sums over sensors are carried in float64.
+ * Errors: INVALID_ARG, SIGMA_RANGE, WORKSPACE (work too small), HIP.
+ */
+gpair_status gpair_assa_adjoint(gpair_plan p, double sigma, const float *delta, float *g,
+                                void *work, size_t work_bytes, gpair_stream stream);
+
+/* ------------------------------------------------------------------------ */
 /* Kernel timing (measurement support)                                        */
 /* ------------------------------------------------------------------------ */
 
 #define GPAIR_TIMER_FORWARD 0 /* main forward kernel of the last forward  */
 #define GPAIR_TIMER_ADJOINT 1 /* main adjoint kernel of the last adjoint  */
+#define GPAIR_TIMER_ASSA_FORWARD 2 /* the ASSA forward kernel             */
+#define GPAIR_TIMER_ASSA_ADJOINT 3 /* the ASSA back-projection kernel     */
+#define GPAIR_TIMER_KINDS 4
 
 #define GPAIR_TIMER_SLOTS 64   /* launches remembered per kind              */
 

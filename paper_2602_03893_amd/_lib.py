@@ -35,6 +35,8 @@ GPAIR_OK = 0
 GPAIR_NOT_CONVERGED = 1
 TIMER_FORWARD = 0
 TIMER_ADJOINT = 1
+TIMER_ASSA_FORWARD = 2
+TIMER_ASSA_ADJOINT = 3
 SOLVE_PGD = 0
 SOLVE_ADAM = 1
 
@@ -116,6 +118,19 @@ class WarmReport(ctypes.Structure):
 
 gpair_warm_rescale = _proto("gpair_warm_rescale", c_i32,
                             [c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(WarmReport), c_vp])
+class AssaGrid(ctypes.Structure):
+    _fields_ = [("n_half", c_i32), ("alpha", c_i32), ("K", c_i32), ("n_fine", c_i32),
+                ("fwd_segment", c_i32), ("fwd_passes", c_i32), ("adj_segment", c_i32),
+                ("adj_stage_sensors", c_i32)]
+
+
+gpair_assa_grid_params = _proto("gpair_assa_grid_params", c_i32,
+                                [c_vp, c_dbl, ctypes.POINTER(AssaGrid)])
+gpair_assa_workspace_size = _proto("gpair_assa_workspace_size", c_i32,
+                                   [c_vp, c_dbl, ctypes.POINTER(ctypes.c_size_t)])
+gpair_assa_forward = _proto("gpair_assa_forward", c_i32, [c_vp, c_vp, c_dbl, c_vp, c_vp])
+gpair_assa_adjoint = _proto("gpair_assa_adjoint", c_i32,
+                            [c_vp, c_dbl, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp])
 gpair_plan_set_timing = _proto("gpair_plan_set_timing", c_i32, [c_vp, ctypes.c_int])
 gpair_plan_kernel_times = _proto("gpair_plan_kernel_times", c_i32,
                                  [c_vp, ctypes.c_int, c_fp, c_i32, ctypes.POINTER(c_i32)])

@@ -162,6 +162,48 @@ class Plan:
             ctypes.byref(rep), _stream()), "gpair_warm_rescale")
         return {"c_star": rep.c_star, "rho": rep.rho, "fell_back": bool(rep.fell_back)}
 
+    # -- ASSA operators (shared sigma) -----------------------------------
+    def assa_grid(self, sigma):
+        """Grid of the ASSA operators for the shared width sigma: dict with
+        n_half, alpha, K, n_fine and the LDS segment lengths."""
+        g = _lib.AssaGrid()
+        check(_lib.gpair_assa_grid_params(self._h, float(sigma), ctypes.byref(g)),
+              "gpair_assa_grid_params")
+        return {f: getattr(g, f) for f, _ in g._fields_}
+
+    def assa_workspace_bytes(self, sigma):
+        n = ctypes.c_size_t()
+        check(_lib.gpair_assa_workspace_size(self._h, float(sigma), ctypes.byref(n)),
+              "gpair_assa_workspace_size")
+        return int(n.value)
+
+    def assa_forward(self, x, sigma, out=None):
+        """y (N_d, N_t) float32 = S(h * P_up(x)) with one shared sigma."""
+        px = _dev(x, "x", self.n_kernels, device=self.device)
+        if out is None:
+            out = torch.empty((self.n_sensors, self.n_samples), dtype=torch.float32,
+                              device=self.device)
+        py = _dev(out, "y", self.n_sensors * self.n_samples, device=self.device)
+        check(_lib.gpair_assa_forward(self._h, px, float(sigma), py, _stream()),
+              "gpair_assa_forward")
+        return out
+
+    def assa_adjoint(self, sigma, delta, out=None, work=None):
+        """g [M] float32 = the transpose of assa_forward applied to delta.
+        `work` (uint8 device tensor of assa_workspace_bytes(sigma) bytes) is
+        allocated here when not given."""
+        pd = _dev(delta, "delta", self.n_sensors * self.n_samples, device=self.device)
+        g = out if out is not None else torch.empty(self.n_kernels, dtype=torch.float32,
+                                                    device=self.device)
+        pg = _dev(g, "g", self.n_kernels, device=self.device)
+        nbytes = self.assa_workspace_bytes(sigma)
+        if work is None:
+            work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        pw = _dev(work, "work", dtype=torch.uint8, device=self.device)
+        check(_lib.gpair_assa_adjoint(self._h, float(sigma), pd, pg, pw, work.numel(),
+                                      _stream()), "gpair_assa_adjoint")
+        return g
+
     def sigma_violations(self):
         n = ctypes.c_int64()
         check(_lib.gpair_sigma_violations(self._h, ctypes.byref(n), _stream()),
@@ -174,8 +216,11 @@ class Plan:
 
     def kernel_times(self, which):
         """Durations (ms) of the main kernel of the recorded calls of kind
-        'forward' or 'adjoint' since the last read (at most 64, oldest first)."""
-        w = {"forward": _lib.TIMER_FORWARD, "adjoint": _lib.TIMER_ADJOINT}[which]
+        'forward', 'adjoint', 'assa_forward' or 'assa_adjoint' since the last
+        read (at most 64, oldest first)."""
+        w = {"forward": _lib.TIMER_FORWARD, "adjoint": _lib.TIMER_ADJOINT,
+             "assa_forward": _lib.TIMER_ASSA_FORWARD,
+             "assa_adjoint": _lib.TIMER_ASSA_ADJOINT}[which]
         buf = (ctypes.c_float * _lib.TIMER_SLOTS)()
         n = ctypes.c_int32()
         check(_lib.gpair_plan_kernel_times(self._h, w, buf, _lib.TIMER_SLOTS, ctypes.byref(n)),

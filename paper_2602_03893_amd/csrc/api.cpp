@@ -45,7 +45,7 @@ gpair_status gpair_plan_create(const gpair_geometry *g, gpair_plan *out) {
     p->ws = nullptr;
     p->ws_bytes = 0;
     p->timing = 0;
-    for (int w = 0; w < 2; ++w) {
+    for (int w = 0; w < GPAIR_TIMER_KINDS; ++w) {
       p->ev_head[w] = p->ev_count[w] = 0;
       for (int i = 0; i < GPAIR_TIMER_SLOTS; ++i) p->ev_start[w][i] = p->ev_stop[w][i] = nullptr;
     }
@@ -111,7 +111,7 @@ gpair_status gpair_plan_bind_workspace(gpair_plan p, void *workspace, size_t wor
 
 void gpair_plan_destroy(gpair_plan p) {
   if (!p) return;
-  for (int w = 0; w < 2; ++w)
+  for (int w = 0; w < GPAIR_TIMER_KINDS; ++w)
     for (int i = 0; i < GPAIR_TIMER_SLOTS; ++i) {
       if (p->ev_start[w][i]) (void)hipEventDestroy(p->ev_start[w][i]);
       if (p->ev_stop[w][i]) (void)hipEventDestroy(p->ev_stop[w][i]);
@@ -172,6 +172,65 @@ gpair_status gpair_adjoint(gpair_plan p, const float *A, const float *sigma,
   timer_begin(p, GPAIR_TIMER_ADJOINT, s);
   e = launch_adjoint(p, delta, gA, gsigma, s);
   timer_end(p, GPAIR_TIMER_ADJOINT, s);
+  return hip_status(e);
+}
+
+gpair_status gpair_assa_grid_params(gpair_plan p, double sigma, gpair_assa_grid *out) {
+  if (!p || !out) return GPAIR_ERR_INVALID_ARG;
+  AssaGrid g;
+  const gpair_status st = assa_grid(p, sigma, &g);
+  if (st != GPAIR_OK) return st;
+  out->n_half = g.n_half;
+  out->alpha = g.alpha;
+  out->K = g.K;
+  out->n_fine = g.n_fine;
+  out->fwd_segment = g.F;
+  out->fwd_passes = (g.Lc + g.Lch - 1) / g.Lch;
+  out->adj_segment = g.Fa;
+  out->adj_stage_sensors = g.S;
+  return GPAIR_OK;
+}
+
+gpair_status gpair_assa_workspace_size(gpair_plan p, double sigma, size_t *bytes) {
+  if (!p || !bytes) return GPAIR_ERR_INVALID_ARG;
+  AssaGrid g;
+  const gpair_status st = assa_grid(p, sigma, &g);
+  if (st != GPAIR_OK) return st;
+  *bytes = assa_work_bytes(p, g);
+  return GPAIR_OK;
+}
+
+gpair_status gpair_assa_forward(gpair_plan p, const float *x, double sigma, float *y,
+                                gpair_stream stream) {
+  if (!bound(p) || !x || !y) return GPAIR_ERR_INVALID_ARG;
+  AssaGrid g;
+  const gpair_status st = assa_grid(p, sigma, &g);
+  if (st != GPAIR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_assa_prep(p, x, s);
+  if (e == hipSuccess) e = launch_fill(y, (int64_t)p->Nd * p->Nt, 0.0f, s);
+  if (e != hipSuccess) return GPAIR_ERR_HIP;
+  timer_begin(p, GPAIR_TIMER_ASSA_FORWARD, s);
+  e = launch_assa_forward(p, g, y, s);
+  timer_end(p, GPAIR_TIMER_ASSA_FORWARD, s);
+  return hip_status(e);
+}
+
+gpair_status gpair_assa_adjoint(gpair_plan p, double sigma, const float *delta, float *g,
+                                void *work, size_t work_bytes, gpair_stream stream) {
+  if (!bound(p) || !delta || !g || !work) return GPAIR_ERR_INVALID_ARG;
+  if (((uintptr_t)work & 255) != 0) return GPAIR_ERR_INVALID_ARG;
+  AssaGrid grid;
+  const gpair_status st = assa_grid(p, sigma, &grid);
+  if (st != GPAIR_OK) return st;
+  if (work_bytes < assa_work_bytes(p, grid)) return GPAIR_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  float *dconv = (float *)work;
+  hipError_t e = launch_assa_dconv(p, grid, delta, dconv, s);
+  if (e != hipSuccess) return GPAIR_ERR_HIP;
+  timer_begin(p, GPAIR_TIMER_ASSA_ADJOINT, s);
+  e = launch_assa_adjoint(p, grid, dconv, g, s);
+  timer_end(p, GPAIR_TIMER_ASSA_ADJOINT, s);
   return hip_status(e);
 }
 
@@ -253,7 +312,7 @@ gpair_status gpair_adam_update(int64_t n, float *x, const float *g, float *m, fl
 gpair_status gpair_plan_set_timing(gpair_plan p, int enable) {
   if (!p) return GPAIR_ERR_INVALID_ARG;
   if (enable) {
-    for (int w = 0; w < 2; ++w)
+    for (int w = 0; w < GPAIR_TIMER_KINDS; ++w)
       for (int i = 0; i < GPAIR_TIMER_SLOTS; ++i) {
         if (!p->ev_start[w][i] && hipEventCreate(&p->ev_start[w][i]) != hipSuccess)
           return GPAIR_ERR_HIP;
@@ -262,14 +321,14 @@ gpair_status gpair_plan_set_timing(gpair_plan p, int enable) {
       }
   }
   p->timing = enable ? 1 : 0;
-  p->ev_head[0] = p->ev_head[1] = p->ev_count[0] = p->ev_count[1] = 0;
+  for (int w = 0; w < GPAIR_TIMER_KINDS; ++w) p->ev_head[w] = p->ev_count[w] = 0;
   return GPAIR_OK;
 }
 
 gpair_status gpair_plan_kernel_times(gpair_plan p, int which, float *ms, int32_t capacity,
                                      int32_t *count) {
   if (!p || !count || capacity < 0 || (capacity > 0 && !ms) ||
-      (which != GPAIR_TIMER_FORWARD && which != GPAIR_TIMER_ADJOINT) || !p->timing)
+      which < 0 || which >= GPAIR_TIMER_KINDS || !p->timing)
     return GPAIR_ERR_INVALID_ARG;
   const int n = p->ev_count[which];
   const int first = (p->ev_head[which] - n + GPAIR_TIMER_SLOTS) % GPAIR_TIMER_SLOTS;

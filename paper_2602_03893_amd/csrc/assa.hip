@@ -1,0 +1,534 @@
+// assa.hip -- gfx950 kernels of the ASSA operators (adaptive supersampling
+// alignment; arXiv 2602.03893, Methods, "Adaptive supersampling alignment for
+// the differentiable model operator", and its Algorithm for the forward and
+// adjoint operators with ASSA).
+//
+// One kernel width sigma shared by all kernels.  The fine-grid index of a
+// kernel-sensor pair is k = floor(r ku + ku0), ku = alpha / (v dt),
+// ku0 = 1/2 - alpha t0 / dt, evaluated in float64 (r as in the direct
+// operators: float64 difference of the float32 coordinates, float32 rsq seed,
+// one float64 Newton step).
+//
+// Forward, fused per (tile, 64 sensors) in one workgroup of four waves:
+//  1. projection P_up: lane = sensor; the waves split the tile's kernels and
+//     add x_i / r_ij into one fine-grid LDS segment per sensor.  The four
+//     waves share the segment, so the adds are LDS atomics; they are integer
+//     adds of a fixed-point value (LDS float atomics measured about three times
+//     slower).  The unit of a column is S / 2^30 with S = sum_tile |x| /
+//     r_low, r_low a lower bound of the tile's distances to that sensor: no
+//     partial sum can overflow, and every impulse is resolved to
+//     2^-31 S (about 1e-7 of an impulse for a uniform tile of 256 kernels).
+//     Within a wave each lane owns its column, so the adds are free of bank
+//     conflicts.  The sums are exact and independent of the order of the adds;
+//     after the projection each column is converted to float in place;
+//  2. transposed convolution with h and decimation, in LDS: coarse sample c
+//     of a column is sum_{q<K} hq[q] (z[alpha c + q] - z[alpha c + 2K - q])
+//     (h is odd and h[0] = 0), written back over the column's first rows;
+//  3. flush: one coalesced float atomic per coarse sample into y, as in the
+//     direct forward.  The write-back rotates row c by c columns so that both
+//     the write-back (lanes along sensors) and the flush reads (lanes along
+//     time) are free of bank conflicts.
+// Adjoint:
+//  1. delta_conv = correlation of the zero-filled residual with h, one
+//     thread per (sensor, sample m) producing the fine samples alpha m + phi;
+//  2. back-projection: one workgroup per tile, lane = kernel.  For each stage
+//     of 64 sensors the tile's shell of delta_conv is staged in LDS; each lane
+//     gathers one value per pair.  float32 within a stage, float64 across
+//     stages, no atomics.
+#include <algorithm>
+#include <cmath>
+
+#include "gpair_internal.h"
+
+namespace gpair {
+namespace {
+
+constexpr int kAssaWaves = 4;         // waves per forward workgroup (one sensor group)
+constexpr int kAssaOut = 16;          // coarse samples per wave per convolution pass
+constexpr int kAssaPass = kAssaWaves * kAssaOut;
+static_assert(kAssaPass == kWave, "one convolution pass covers 64 coarse samples");
+
+__device__ __forceinline__ int64_t xcd_logical(int64_t nlogical) {
+  const int64_t per = (nlogical + kXcds - 1) / kXcds;
+  const int64_t b = blockIdx.x;
+  return (b % kXcds) * per + b / kXcds;
+}
+
+inline unsigned int xcd_blocks(int64_t nlogical) {
+  const int64_t per = (nlogical + kXcds - 1) / kXcds;
+  return (unsigned int)(per * kXcds);
+}
+
+// floor(a / b) for b > 0.
+__device__ __forceinline__ int floor_div(int a, int b) {
+  return a >= 0 ? a / b : -((-a + b - 1) / b);
+}
+
+// Distance r (float64) and the float32 rsq seed 1/r of one pair.
+struct Dist {
+  double r;
+  float rinv;
+};
+
+__device__ __forceinline__ Dist pair_dist(double sx, double sy, double sz, double cx,
+                                          double cy, double cz) {
+  const double ex = sx - cx, ey = sy - cy, ez = sz - cz;
+  const double r2 = fma(ez, ez, fma(ey, ey, ex * ex));
+  const float y0 = __builtin_amdgcn_rsqf((float)r2);
+  const double y0d = (double)y0;
+  const double r0 = r2 * y0d;
+  const double res = fma(-r0, r0, r2);
+  Dist d;
+  d.r = fma(res, 0.5 * y0d, r0);
+  d.rinv = y0;
+  return d;
+}
+
+// Lower bound (minus one) of the fine index of any pair of a tile whose
+// members lie within rho of the tile centre at distance R from the sensor.
+__device__ __forceinline__ int shell_low(double R, double rho, double ku, double ku0) {
+  return (int)floor(fma(R - rho, ku, ku0)) - 1;
+}
+
+// ---------------------------------------------------------------------------
+// Amplitudes into the kernel records (permuted order).
+// ---------------------------------------------------------------------------
+// One workgroup per forward tile: the members' amplitudes into their records
+// and the tile's sum of |x| into its TileInfo (the fixed-point scale).
+__global__ __launch_bounds__(256) void assa_prep_kernel(const float *__restrict__ x,
+                                                        const int32_t *__restrict__ perm,
+                                                        KernelRec *__restrict__ rec,
+                                                        TileInfo *__restrict__ tiles) {
+  __shared__ float part[256 / kWave];
+  TileInfo &T = tiles[blockIdx.x];
+  const int start = T.start, count = T.count;
+  float acc = 0.0f;
+  for (int i = threadIdx.x; i < count; i += 256) {
+    const float v = x[perm[start + i]];
+    rec[start + i].amp = v;
+    acc += fabsf(v);
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) T.asum = (part[0] + part[1]) + (part[2] + part[3]);
+}
+
+// ---------------------------------------------------------------------------
+// Forward.
+// ---------------------------------------------------------------------------
+struct AssaFwdArgs {
+  const double4 *sens;
+  const TileInfo *tiles;
+  float *y;
+  int64_t nlogical;
+  int32_t Nd, Nt, nsg, nfine, alpha, K;
+  int32_t Lc;   // coarse samples of a (tile, sensor) shell
+  int32_t Lch;  // coarse samples per pass (Lc when the whole shell fits in LDS)
+  int32_t F;    // fine rows of the LDS segment: alpha (Lch - 1) + 2K + 1
+  double ku, ku0;
+  double min_dist;      // lower bound of every kernel-sensor distance (m)
+  float hq[kAssaMaxK];  // hq[q] = h(K - q), q = 0 .. K-1
+};
+
+// The impulse of one pair for the pass whose rows start at fine point fbc:
+// its row (clamped into [0, F)) and fixed-point value x / r * inv_unit
+// (zero when the fine point is outside [0, nfine) or outside the pass's rows,
+// so the add is harmless).
+struct Impulse {
+  int row;
+  int val;
+};
+
+__device__ __forceinline__ Impulse impulse(const double4 &s, const KernelRec &r, int fbc,
+                                           int F, double ku, double ku0, double nfine,
+                                           float inv_unit) {
+  const Dist d = pair_dist(s.x, s.y, s.z, r.cx, r.cy, r.cz);
+  const double kd = floor(fma(d.r, ku, ku0));  // |kd| < 1e9 (checked on the host)
+  const int pp = (int)kd - fbc;
+  const bool in = kd >= 0.0 && kd < nfine && (unsigned)pp < (unsigned)F;
+  Impulse o;
+  o.row = min(max(pp, 0), F - 1);
+  o.val = in ? (int)rintf(r.amp * d.rinv * inv_unit) : 0;
+  return o;
+}
+
+__device__ __forceinline__ void lds_add(int *p, int v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__global__ __launch_bounds__(kAssaWaves * kWave) void assa_forward_kernel(
+    const KernelRec *__restrict__ krec, AssaFwdArgs a) {
+  extern __shared__ float seg[];  // [F][64]: fine row p of sensor column l at p*64 + l
+  __shared__ float hqs[kAssaMaxK];
+
+  const int64_t logical = xcd_logical(a.nlogical);
+  if (logical >= a.nlogical) return;
+  const int64_t tile = logical / a.nsg;
+  const int sg = (int)(logical - tile * a.nsg);
+  const int t = threadIdx.x;
+  const int lane = t & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int j = sg * kWave + lane;
+  const double4 s = a.sens[j < a.Nd ? j : a.Nd - 1];
+  const TileInfo T = a.tiles[tile];
+
+  // Shell of the lane's sensor: coarse sample c is the sampling-grid point
+  // nb + c and reads the fine points fb + [alpha c, alpha c + 2K], with
+  // fb = alpha nb - K.  Every impulse of the tile has fine point >= fb + 2K,
+  // and every coarse sample it reaches is < Lc (host bound on Lc).
+  int nb, fb;
+  float inv_unit, unit;  // fixed-point scale of the lane's column
+  {
+    const double dx = s.x - T.cx, dy = s.y - T.cy, dz = s.z - T.cz;
+    const double R = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
+    nb = floor_div(shell_low(R, T.rho, a.ku, a.ku0) - a.K, a.alpha);
+    fb = nb * a.alpha - a.K;
+    // Every pair distance of the tile is >= r_low, so |sum of the column's
+    // impulses| <= asum / r_low = 2^30 units.
+    const double r_low = fmax(R - T.rho, a.min_dist);
+    const double bound = (double)T.asum / r_low;
+    unit = (float)(bound * 0x1p-30);
+    inv_unit = bound > 0.0 ? (float)(0x1p30 / bound) : 0.0f;
+  }
+  float *const col = seg + lane;
+  int *const icol = reinterpret_cast<int *>(seg) + lane;
+  const int per = (T.count + kAssaWaves - 1) / kAssaWaves;
+  const int k0 = T.start + wave * per;
+  const int k1 = min(T.start + T.count, k0 + per);
+  const double nfine = (double)a.nfine;
+  const int twoK = 2 * a.K;
+
+  // Passes over the shell, Lch coarse samples each (one pass unless the
+  // shell's fine rows exceed the LDS budget).  Pass cc needs the impulses of
+  // fine rows [alpha cc, alpha (cc + Lch - 1) + 2K], i.e. rows [0, F) of its
+  // segment; impulses in the overlap of two passes are added in both, each
+  // time reaching only that pass's coarse samples.
+  for (int cc = 0; cc < a.Lc; cc += a.Lch) {
+    const int nc = min(a.Lch, a.Lc - cc);
+    const int fbc = fb + a.alpha * cc;
+    if (cc > 0) __syncthreads();  // the previous pass's flush has read the segment
+    {
+      float4 *s4 = reinterpret_cast<float4 *>(seg);
+      const int n4 = a.F * (kWave / 4);
+      for (int i = t; i < n4; i += kAssaWaves * kWave) s4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (cc == 0)
+        for (int i = t; i < a.K; i += kAssaWaves * kWave) hqs[i] = a.hq[i];
+    }
+    __syncthreads();
+
+    // 1. Projection: wave w takes a contiguous quarter of the tile's kernels,
+    //    two pairs per iteration in one straight-line block so that their
+    //    float64 chains interleave; the next two records are fetched before
+    //    the LDS adds are issued.
+    if (k0 < k1) {
+      const int last = k1 - 1;
+      KernelRec ra = krec[k0], rb = krec[min(k0 + 1, last)];
+      int k = k0;
+      for (; k + 1 < k1; k += 2) {
+        const Impulse ia = impulse(s, ra, fbc, a.F, a.ku, a.ku0, nfine, inv_unit);
+        const Impulse ib = impulse(s, rb, fbc, a.F, a.ku, a.ku0, nfine, inv_unit);
+        ra = krec[min(k + 2, last)];
+        rb = krec[min(k + 3, last)];
+        lds_add(icol + ia.row * kWave, ia.val);
+        lds_add(icol + ib.row * kWave, ib.val);
+      }
+      if (k < k1) {
+        const Impulse ia = impulse(s, ra, fbc, a.F, a.ku, a.ku0, nfine, inv_unit);
+        lds_add(icol + ia.row * kWave, ia.val);
+      }
+    }
+    __syncthreads();
+    // Fixed point to float, in place: wave w converts rows w, w + 4, ...
+    for (int row = wave; row < a.F; row += kAssaWaves)
+      col[row * kWave] = (float)icol[row * kWave] * unit;
+    __syncthreads();
+
+    // 2. Convolution and decimation, 64 coarse samples per round (16 per
+    //    wave).  Round r writes rows [64r, 64r + 64) once every wave has read
+    //    its inputs; later rounds read rows >= alpha (64r + 64), so nothing
+    //    they need is overwritten.
+    for (int c0 = 0; c0 < nc; c0 += kAssaPass) {
+      const int cw = c0 + wave * kAssaOut;
+      const int nu = min(kAssaOut, nc - cw);  // may be <= 0
+      float acc[kAssaOut];
+#pragma unroll
+      for (int u = 0; u < kAssaOut; ++u) acc[u] = 0.0f;
+      if (nu > 0) {
+        const float *base = col + (size_t)a.alpha * cw * kWave;
+        const int ustep = a.alpha * kWave;
+        for (int q = 0; q < a.K; ++q) {
+          const float hq = hqs[q];
+          const float *lo = base + q * kWave;
+          const float *hi = base + (twoK - q) * kWave;
+#pragma unroll
+          for (int u = 0; u < kAssaOut; ++u)
+            if (u < nu) acc[u] = fmaf(hq, lo[u * ustep] - hi[u * ustep], acc[u]);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < kAssaOut; ++u)
+        if (u < nu) {
+          const int c = cw + u;
+          seg[c * kWave + ((lane + c) & (kWave - 1))] = acc[u];
+        }
+      __syncthreads();
+    }
+
+    // 3. Flush: wave w adds the rows of sensors w, w + 4, ...; lanes walk the
+    //    coarse samples of one sensor (consecutive addresses of y).
+    for (int row = wave; row < kWave; row += kAssaWaves) {
+      const int jr = sg * kWave + row;
+      if (jr >= a.Nd) break;
+      const int nbr = __builtin_amdgcn_readlane(nb, row) + cc;
+      float *yrow = a.y + (int64_t)jr * a.Nt;
+      for (int c = lane; c < nc; c += kWave) {
+        const int n = nbr + c;
+        const float v = seg[c * kWave + ((row + c) & (kWave - 1))];
+        if (n >= 0 && n < a.Nt && v != 0.0f) unsafeAtomicAdd(yrow + n, v);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint, step 1: delta_conv[j][alpha m + phi] =
+//   sum_t h(alpha t - phi) delta[j][m + t],  |alpha t - phi| <= K.
+// ---------------------------------------------------------------------------
+struct AssaConvArgs {
+  const float *delta;
+  float *dconv;
+  int64_t total;  // Nd * Nt
+  int32_t Nt, nfine, alpha, K, n_half;
+  float h[2 * kAssaMaxK + 1];  // h(m) at index m + K
+};
+
+__global__ __launch_bounds__(256) void assa_dconv_kernel(AssaConvArgs a) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= a.total) return;
+  const int64_t j = idx / a.Nt;
+  const int m = (int)(idx - j * a.Nt);
+  const float *d = a.delta + j * a.Nt;
+  float *out = a.dconv + j * a.nfine + (int64_t)a.alpha * m;
+  for (int phi = 0; phi < a.alpha; ++phi) {
+    float acc = 0.0f;
+    const int tlo = phi > 0 ? 1 - a.n_half : -a.n_half;
+    for (int tt = tlo; tt <= a.n_half; ++tt) {
+      const int n = m + tt;
+      if (n >= 0 && n < a.Nt) acc = fmaf(a.h[a.alpha * tt - phi + a.K], d[n], acc);
+    }
+    out[phi] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint, step 2: back-projection g_i = sum_j delta_conv_j[k_ij] / r_ij.
+// ---------------------------------------------------------------------------
+struct AssaAdjArgs {
+  const KernelRec *krec;
+  const TileInfo *tiles;
+  const int32_t *perm;
+  const float *dconv;
+  float *out;
+  int64_t nlogical;
+  int32_t Nd, nfine, Fa;
+  int32_t S;  // sensors per stage (<= kAdjSensorsPerStage; fewer when Fa is long)
+  double ku, ku0;
+};
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void assa_adjoint_kernel(const double4 *__restrict__ sens,
+                                                            AssaAdjArgs a) {
+  extern __shared__ float stage[];  // [S][Fa]
+  __shared__ int kbs[kAdjSensorsPerStage];
+
+  const int64_t logical = xcd_logical(a.nlogical);
+  if (logical >= a.nlogical) return;
+  const TileInfo T = a.tiles[logical];
+  const int t = threadIdx.x;
+  const int lane = t & (kWave - 1);
+  const int wave = t >> 6;
+  const bool live = t < T.count;
+  const int64_t i = T.start + (live ? t : 0);
+  const KernelRec r = a.krec[i];
+  const int pmax = a.Fa - 1;
+
+  double acc = 0.0;
+  for (int j0 = 0; j0 < a.Nd; j0 += a.S) {
+    const int nsb = min(a.S, a.Nd - j0);
+    __syncthreads();  // the previous stage has been consumed
+    if (t < nsb) {
+      const double4 s = sens[j0 + t];
+      const double dx = s.x - T.cx, dy = s.y - T.cy, dz = s.z - T.cz;
+      const double R = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
+      kbs[t] = shell_low(R, T.rho, a.ku, a.ku0);
+    }
+    __syncthreads();
+    // Stage the fine-grid shell: one wave per row, lanes along the row;
+    // points outside [0, nfine) read as zero (those pairs are dropped).
+    for (int js = wave; js < nsb; js += BLOCK / kWave) {
+      const float *drow = a.dconv + (int64_t)(j0 + js) * a.nfine;
+      const int kb = kbs[js];
+      for (int c = lane; c < a.Fa; c += kWave) {
+        const int k = kb + c;
+        stage[js * a.Fa + c] = (k >= 0 && k < a.nfine) ? drow[k] : 0.0f;
+      }
+    }
+    __syncthreads();
+
+    float p = 0.0f;
+    for (int js = 0; js < nsb; ++js) {
+      const double4 s = sens[j0 + js];
+      const Dist d = pair_dist(s.x, s.y, s.z, r.cx, r.cy, r.cz);
+      const double kd = floor(fma(d.r, a.ku, a.ku0));
+      // kd - kb is in [1, Fa - 1] by construction of kb and Fa (clamped only
+      // to keep the read in the stage were that ever violated).
+      const int pp = min(max((int)kd - kbs[js], 0), pmax);
+      p = fmaf(stage[js * a.Fa + pp], d.rinv, p);
+    }
+    acc += (double)p;
+  }
+  if (live) a.out[a.perm[i]] = (float)acc;
+}
+
+double max_tile_rho(const std::vector<TileInfo> &tiles) {
+  double r = 0.0;
+  for (const TileInfo &t : tiles) r = std::max(r, t.rho);
+  return r;
+}
+
+// h(m) = (1/2) d exp(-d^2 / (2 sigma^2)), d = -v m dt / alpha, m = -K..K.
+double assa_h(const gpair_plan_s *p, const AssaGrid &g, int m) {
+  const double d = -p->v * (double)m * (p->dt / (double)g.alpha);
+  return 0.5 * d * std::exp(-(d * d) / (2.0 * g.sigma * g.sigma));
+}
+
+}  // namespace
+
+gpair_status assa_grid(const gpair_plan_s *p, double sigma, AssaGrid *g) {
+  if (!std::isfinite(sigma) || !(sigma > 0.0) || sigma > p->sigma_max)
+    return GPAIR_ERR_SIGMA_RANGE;
+  const double x = p->nsig * sigma / p->vdt;
+  const double nh = std::max(1.0, std::ceil(x - 1e-9 * std::max(1.0, x)));
+  if (!(nh <= (double)kAssaMaxK)) return GPAIR_ERR_INVALID_ARG;
+  AssaGrid o{};
+  o.sigma = sigma;
+  o.n_half = (int32_t)nh;
+  o.alpha = std::max(1, (int32_t)std::ceil(12.0 / nh));
+  o.K = o.alpha * o.n_half;
+  if (o.K > kAssaMaxK) return GPAIR_ERR_INVALID_ARG;
+  const int64_t nfine = (int64_t)o.alpha * p->Nt;
+  if (nfine >= (int64_t(1) << 30)) return GPAIR_ERR_INVALID_ARG;
+  o.n_fine = (int32_t)nfine;
+  // Every fine index the kernels form must stay well inside int range.
+  double smax = 0.0, cmax = 0.0;
+  for (int32_t j = 0; j < p->Nd; ++j) {
+    const double *s = &p->host.sens[4 * (size_t)j];
+    smax = std::max(smax, std::sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]));
+  }
+  for (const TileInfo &t : p->host.ftiles)
+    cmax = std::max(cmax, std::sqrt(t.cx * t.cx + t.cy * t.cy + t.cz * t.cz) + t.rho);
+  const double ku = (double)o.alpha / p->vdt;
+  const double ku0 = 0.5 - (double)o.alpha * p->t0 / p->dt;
+  if (!((smax + cmax) * ku + std::fabs(ku0) + 8.0 * (o.K + 2) < 1e9))
+    return GPAIR_ERR_INVALID_ARG;
+  const double rf = max_tile_rho(p->host.ftiles), ra = max_tile_rho(p->host.atiles);
+  const double lc = std::ceil(2.0 * rf * p->inv_vdt + 2.0 * nh) + 4.0;
+  const double fa = std::ceil(2.0 * o.alpha * ra * p->inv_vdt) + 4.0;
+  if (!(lc < 1e6 && fa < 1e6)) return GPAIR_ERR_INVALID_ARG;
+  o.Lc = (int32_t)lc;
+  // Forward: the whole shell in one pass if its fine rows fit, else passes of
+  // Lch coarse samples with alpha (Lch - 1) + 2K + 1 <= the LDS rows.
+  const int rows = kMaxSegmentBytes / (kWave * 4);
+  const int full = o.alpha * (o.Lc - 1) + 2 * o.K + 1;
+  o.Lch = full <= rows ? o.Lc : (rows - 2 * o.K - 1) / o.alpha + 1;
+  if (o.Lch < 1) return GPAIR_ERR_INVALID_ARG;
+  o.F = o.alpha * (o.Lch - 1) + 2 * o.K + 1;
+  // Adjoint: as many sensors per stage as fit, at most kAdjSensorsPerStage.
+  o.Fa = (int32_t)fa;
+  o.S = std::min<int64_t>(kAdjSensorsPerStage, kMaxSegmentBytes / (4 * (int64_t)o.Fa));
+  if (o.S < 1) return GPAIR_ERR_INVALID_ARG;
+  *g = o;
+  return GPAIR_OK;
+}
+
+size_t assa_work_bytes(const gpair_plan_s *p, const AssaGrid &g) {
+  return (size_t)p->Nd * (size_t)g.n_fine * sizeof(float);
+}
+
+hipError_t launch_assa_prep(const gpair_plan_s *p, const float *x, hipStream_t s) {
+  const unsigned int grid = (unsigned int)p->host.ftiles.size();
+  assa_prep_kernel<<<grid, 256, 0, s>>>(x, ws_perm(p), ws_krec(p), ws_ftiles(p));
+  return hipGetLastError();
+}
+
+hipError_t launch_assa_forward(const gpair_plan_s *p, const AssaGrid &g, float *y,
+                               hipStream_t s) {
+  AssaFwdArgs a{};
+  a.sens = (const double4 *)ws_sens(p);
+  a.tiles = ws_ftiles(p);
+  a.y = y;
+  a.Nd = p->Nd;
+  a.Nt = p->Nt;
+  a.nsg = (p->Nd + kWave - 1) / kWave;
+  a.nlogical = (int64_t)p->host.ftiles.size() * a.nsg;
+  a.nfine = g.n_fine;
+  a.alpha = g.alpha;
+  a.K = g.K;
+  a.Lc = g.Lc;
+  a.Lch = g.Lch;
+  a.F = g.F;
+  a.ku = (double)g.alpha / p->vdt;
+  a.ku0 = 0.5 - (double)g.alpha * p->t0 / p->dt;
+  a.min_dist = p->min_dist;
+  for (int q = 0; q < g.K; ++q) a.hq[q] = (float)assa_h(p, g, g.K - q);
+  const size_t lds = (size_t)g.F * kWave * sizeof(float);
+  assa_forward_kernel<<<xcd_blocks(a.nlogical), kAssaWaves * kWave, lds, s>>>(ws_krec(p), a);
+  return hipGetLastError();
+}
+
+hipError_t launch_assa_dconv(const gpair_plan_s *p, const AssaGrid &g, const float *delta,
+                             float *dconv, hipStream_t s) {
+  AssaConvArgs a{};
+  a.delta = delta;
+  a.dconv = dconv;
+  a.total = (int64_t)p->Nd * p->Nt;
+  a.Nt = p->Nt;
+  a.nfine = g.n_fine;
+  a.alpha = g.alpha;
+  a.K = g.K;
+  a.n_half = g.n_half;
+  for (int m = -g.K; m <= g.K; ++m) a.h[m + g.K] = (float)assa_h(p, g, m);
+  const unsigned int grid = (unsigned int)((a.total + 255) / 256);
+  assa_dconv_kernel<<<grid, 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_assa_adjoint(const gpair_plan_s *p, const AssaGrid &g, const float *dconv,
+                               float *out, hipStream_t s) {
+  AssaAdjArgs a{};
+  a.krec = ws_krec(p);
+  a.tiles = ws_atiles(p);
+  a.perm = ws_perm(p);
+  a.dconv = dconv;
+  a.out = out;
+  a.nlogical = (int64_t)p->host.atiles.size();
+  a.Nd = p->Nd;
+  a.nfine = g.n_fine;
+  a.Fa = g.Fa;
+  a.S = g.S;
+  a.ku = (double)g.alpha / p->vdt;
+  a.ku0 = 0.5 - (double)g.alpha * p->t0 / p->dt;
+  const size_t lds = (size_t)g.Fa * g.S * sizeof(float);
+  const unsigned int grid = xcd_blocks(a.nlogical);
+  const double4 *sens = (const double4 *)ws_sens(p);
+  switch (p->adj_tile) {
+    case 64: assa_adjoint_kernel<64><<<grid, 64, lds, s>>>(sens, a); break;
+    case 128: assa_adjoint_kernel<128><<<grid, 128, lds, s>>>(sens, a); break;
+    default: assa_adjoint_kernel<256><<<grid, 256, lds, s>>>(sens, a); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gpair

@@ -18,7 +18,9 @@ struct alignas(16) TileInfo {
   double rho;         // sphere radius (m): every member is within rho
   int32_t start;      // first member in permuted order
   int32_t count;      // number of members (<= the tile size)
-  int32_t pad0, pad1;
+  float asum;         // per-call scratch of the ASSA forward: sum of |x| over
+                      // the members (forward tiles only)
+  int32_t pad1;
 };
 static_assert(sizeof(TileInfo) == 48, "TileInfo layout");
 
@@ -84,10 +86,10 @@ struct gpair_plan_s {
   size_t ws_bytes;
   // timing: per kind (forward, adjoint) a ring of event pairs
   int timing;
-  hipEvent_t ev_start[2][GPAIR_TIMER_SLOTS];
-  hipEvent_t ev_stop[2][GPAIR_TIMER_SLOTS];
-  int ev_head[2];
-  int ev_count[2];
+  hipEvent_t ev_start[GPAIR_TIMER_KINDS][GPAIR_TIMER_SLOTS];
+  hipEvent_t ev_stop[GPAIR_TIMER_KINDS][GPAIR_TIMER_SLOTS];
+  int ev_head[GPAIR_TIMER_KINDS];
+  int ev_count[GPAIR_TIMER_KINDS];
 };
 
 namespace gpair {
@@ -113,6 +115,29 @@ hipError_t launch_pgd(int64_t n, float *x, const float *g, float step, float lo,
 hipError_t launch_adam(int64_t n, float *x, const float *g, float *m, float *v,
                        float grad_scale, float lr, float beta1, float beta2,
                        float eps, int32_t t, float lo, float hi, hipStream_t s);
+
+// ASSA operators (assa.hip).  AssaGrid holds the grid of one shared sigma and
+// the LDS segment sizes that follow from the plan's tiles.
+constexpr int kAssaMaxK = 120;  // h has at most 2 kAssaMaxK + 1 taps (fits the LDS rows)
+struct AssaGrid {
+  int32_t n_half, alpha, K, n_fine;
+  int32_t Lc;   // coarse samples of a forward (tile, sensor) shell
+  int32_t Lch;  // coarse samples per forward pass
+  int32_t F;    // fine rows per forward LDS segment (alpha (Lch - 1) + 2K + 1)
+  int32_t Fa;   // fine samples per adjoint stage row
+  int32_t S;    // sensors per adjoint stage
+  double sigma;
+};
+// Grid of `sigma` for plan p; GPAIR_OK or the status to return.
+gpair_status assa_grid(const gpair_plan_s *p, double sigma, AssaGrid *g);
+size_t assa_work_bytes(const gpair_plan_s *p, const AssaGrid &g);
+hipError_t launch_assa_prep(const gpair_plan_s *p, const float *x, hipStream_t s);
+hipError_t launch_assa_forward(const gpair_plan_s *p, const AssaGrid &g, float *y,
+                               hipStream_t s);
+hipError_t launch_assa_dconv(const gpair_plan_s *p, const AssaGrid &g, const float *delta,
+                             float *dconv, hipStream_t s);
+hipError_t launch_assa_adjoint(const gpair_plan_s *p, const AssaGrid &g, const float *dconv,
+                               float *out, hipStream_t s);
 
 // Workspace pointers of a bound plan.
 inline double *ws_sens(const gpair_plan_s *p) { return (double *)(p->ws + p->lay.sens); }
