@@ -78,6 +78,129 @@ def cpu_baseline(w, centres, sensors, A, sigma_val, rows=32, stride=32):
 
 PEAK_BF16_TFLOPS = 2500.0  # MI355X dense bf16 matrix peak (published)
 
+# ASSA operators: algorithmic FLOPs per kernel-sensor pair (distance 7 with the
+# square root as one, snapped index 3, x / r 1, add or multiply-accumulate 2)
+# and per decimated output sample (the 2K + 1 taps of h, multiply-add each).
+FLOP_PAIR_ASSA = 13
+# The paper's ASSA operator times at this workload (RTX 5090): context only.
+PAPER_ASSA_MS = {"forward": 37.41, "adjoint": 4.99}
+
+
+def cpu_baseline_assa(w, centres, sensors, x, sigma, rows=16, stride=64):
+    """The float64 ASSA oracle on a bounded sample of the workload: the
+    forward for `rows` sensors (all kernels), the back-projection for every
+    `stride`-th kernel (all sensors)."""
+    import numpy as np
+    from oracle import assa as S
+    from oracle import ops as O
+    from paper_2602_03893_amd import inputs as I
+    g = O.Geometry(centres, sensors, w.n_samples, w.dt, w.t0, w.c_sound, w.n_sigma)
+    M, Nd = w.n_kernels, w.n_sensors
+    pick = np.linspace(0, Nd - 1, rows).astype(int)
+    t = time.perf_counter()
+    S.forward(g.subset_sensors(pick), x.astype(np.float64), sigma)
+    t_fwd = time.perf_counter() - t
+    ks = np.arange(0, M, stride)
+    delta = I.standard_normal((Nd, w.n_samples), seed=99, dtype=np.float64)
+    t = time.perf_counter()
+    S.adjoint(g.subset_kernels(ks), sigma, delta)
+    t_adj = time.perf_counter() - t
+    rate = (M * rows + len(ks) * Nd) / (t_fwd + t_adj) / 1e9
+    return {"value": rate, "unit": "G-evals/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": (f"float64 ASSA oracle: forward on {rows} of {Nd} sensors x {M} kernels "
+                       f"({t_fwd:.2f} s) + back-projection on {len(ks)} kernels x {Nd} sensors "
+                       f"({t_adj:.2f} s); rate = pairs / time")}
+
+
+def bench_assa(args):
+    """Paper-scale IR step with the ASSA operators (one shared sigma, the
+    paper's own discretisation): forward -> residual -> back-projection ->
+    Adam on A (A >= 0)."""
+    import numpy as np
+    import torch
+    from paper_2602_03893_amd import Plan, adam_update, inputs as I
+
+    w = I.WORKLOADS[args.workload]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    centres, sensors = I.geometry_arrays(w)
+    t = time.perf_counter()
+    plan = Plan(centres, sensors, w.n_samples, w.dt, w.c_sound, n_sigma=w.n_sigma,
+                sigma_max=w.smax, device=dev)
+    t_plan = time.perf_counter() - t
+    sig = w.sigma
+    grid = plan.assa_grid(sig)
+    log(f"bench --assa: workload {w.name}, sigma {sig} m, grid {grid}, plan {t_plan:.2f} s")
+    M, Nd, Nt = w.n_kernels, w.n_sensors, w.n_samples
+    A_true_h = I.phantom(w)
+    b = plan.assa_forward(torch.tensor(A_true_h, device=dev), sig).clone()
+    A = torch.zeros(M, dtype=torch.float32, device=dev)
+    mA, vA = torch.zeros_like(A), torch.zeros_like(A)
+    y = torch.empty((Nd, Nt), dtype=torch.float32, device=dev)
+    gA = torch.empty(M, dtype=torch.float32, device=dev)
+    work = torch.empty(plan.assa_workspace_bytes(sig), dtype=torch.uint8, device=dev)
+    scale = 1.0 / float(torch.sum(b.double() ** 2))
+    state = {"t": 0}
+
+    def step():
+        state["t"] += 1
+        plan.assa_forward(A, sig, out=y)
+        plan.residual(y, b, scale=scale, delta=y)
+        plan.assa_adjoint(sig, y, out=gA, work=work)
+        adam_update(A, gA, mA, vA, state["t"], 1e-2, lo=0.0)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    f_ms = float(np.mean(plan.kernel_times("assa_forward")))
+    a_ms = float(np.mean(plan.kernel_times("assa_adjoint")))
+    plan.set_timing(False)
+    pairs = float(M) * Nd
+    ms_step = 1e3 * elapsed / args.steps
+    value = 2.0 * pairs * args.steps / elapsed / 1e9
+    flop_fwd = FLOP_PAIR_ASSA * pairs + 2.0 * (2 * grid["K"] + 1) * Nd * Nt
+    achieved = flop_fwd / (f_ms * 1e-3) / 1e12
+    log(f"bench --assa: {ms_step:.2f} ms/step, forward kernel {f_ms:.2f} ms, back-projection "
+        f"kernel {a_ms:.2f} ms, {value:.1f} G-evals/s")
+    out = {
+        "metric": "fwd+adjoint G-evals/s (paper-scale IR step, ASSA operators)",
+        "value": value,
+        "unit": "G-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 snapped index / int32 fixed-point impulses / f32 convolution and sums",
+        "data": "synthetic (seeded vessel-tree phantom; b = ASSA forward of x_true)",
+        "config": {"workload": "256x256x128 Gaussian kernels (0.1 mm), 1024 sensors on a "
+                               "40 mm hemisphere, 4096 samples at 40 MHz, shared sigma "
+                               f"{sig} m (alpha {grid['alpha']}, K {grid['K']}), Adam on A",
+                   "kernels": M, "sensors": Nd, "samples": Nt, "parallelism": "single GPU"},
+        "fwd_kernel_ms": f_ms,
+        "adj_kernel_ms": a_ms,
+        "paper_context": {"gpu": "RTX 5090", "fwd_ms": PAPER_ASSA_MS["forward"],
+                          "adj_ms": PAPER_ASSA_MS["adjoint"]},
+        "plan_s": t_plan,
+        "roofline": {"bound": "alu", "kernel": "assa_forward_kernel", "achieved": achieved,
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        log("bench --assa: timing the float64 ASSA oracle on a sample (cpu_baseline)")
+        out["cpu_baseline"] = cpu_baseline_assa(w, centres, sensors, A_true_h, sig)
+    print(json.dumps(out), flush=True)
+
+
 
 def net_flops(levels, n, d, h, w):
     """Algorithmic FLOPs of one training step of the warm-start U-Net (forward,
@@ -201,6 +324,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--net", action="store_true",
                     help="benchmark the warm-start U-Net training step instead")
+    ap.add_argument("--assa", action="store_true",
+                    help="benchmark the IR step with the ASSA operators (shared sigma)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 256 MiB device buffer 3 times (scale reference "
                          "for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -221,6 +346,9 @@ def main():
         sys.exit(2)
     if args.net:
         bench_net(args)
+        return
+    if args.assa:
+        bench_assa(args)
         return
 
     import numpy as np

@@ -5,9 +5,14 @@
 //
 // One kernel width sigma shared by all kernels.  The fine-grid index of a
 // kernel-sensor pair is k = floor(r ku + ku0), ku = alpha / (v dt),
-// ku0 = 1/2 - alpha t0 / dt, evaluated in float64 (r as in the direct
-// operators: float64 difference of the float32 coordinates, float32 rsq seed,
-// one float64 Newton step).
+// ku0 = 1/2 - alpha t0 / dt, evaluated in float64: r^2 = |s|^2 + |c|^2 - 2 s.c
+// from the float64 copies of the float32 coordinates (|s|^2 and |c|^2 are
+// precomputed, so a pair costs one add and three fused multiply-adds; the
+// terms are at most a few times r^2, so the relative error stays ~1e-15),
+// then r from a float32 rsq seed and one float64 Newton step.  The offset of
+// the LDS segment is folded into the constant of the snap, so that one
+// truncating conversion yields the row (the folded value is >= 0 wherever the
+// row is used, where truncation and floor agree).
 //
 // Forward, fused per (tile, 64 sensors) in one workgroup of four waves:
 //  1. projection P_up: lane = sensor; the waves split the tile's kernels and
@@ -70,10 +75,10 @@ struct Dist {
   float rinv;
 };
 
-__device__ __forceinline__ Dist pair_dist(double sx, double sy, double sz, double cx,
-                                          double cy, double cz) {
-  const double ex = sx - cx, ey = sy - cy, ez = sz - cz;
-  const double r2 = fma(ez, ez, fma(ey, ey, ex * ex));
+// r^2 = (|s|^2 + |c|^2) - 2 s.c with m2x = -2 s_x (or -2 c_x), ...
+__device__ __forceinline__ Dist pair_dist(double m2x, double m2y, double m2z, double cx,
+                                          double cy, double cz, double s2c2) {
+  const double r2 = fma(m2x, cx, fma(m2y, cy, fma(m2z, cz, s2c2)));
   const float y0 = __builtin_amdgcn_rsqf((float)r2);
   const double y0d = (double)y0;
   const double r0 = r2 * y0d;
@@ -104,8 +109,10 @@ __global__ __launch_bounds__(256) void assa_prep_kernel(const float *__restrict_
   const int start = T.start, count = T.count;
   float acc = 0.0f;
   for (int i = threadIdx.x; i < count; i += 256) {
+    KernelRec &r = rec[start + i];
     const float v = x[perm[start + i]];
-    rec[start + i].amp = v;
+    r.amp = v;
+    r.h = fma(r.cz, r.cz, fma(r.cy, r.cy, r.cx * r.cx));  // |c|^2
     acc += fabsf(v);
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
@@ -131,25 +138,32 @@ struct AssaFwdArgs {
   float hq[kAssaMaxK];  // hq[q] = h(K - q), q = 0 .. K-1
 };
 
-// The impulse of one pair for the pass whose rows start at fine point fbc:
-// its row (clamped into [0, F)) and fixed-point value x / r * inv_unit
-// (zero when the fine point is outside [0, nfine) or outside the pass's rows,
-// so the add is harmless).
+// Per-lane constants of the projection in one pass.
+struct Lane {
+  double m2x, m2y, m2z;  // -2 s
+  double s2;             // |s|^2
+  double cst;            // ku0 - fbc + 1: u1 = r ku + cst = (fine index - fbc) + 1
+  int plo, pspan;        // u1 truncates into [plo, plo + pspan) iff the fine point is in
+                         // [0, nfine) and in the pass's rows [0, F)
+  float inv_unit;        // fixed-point scale of the column
+};
+
+// The impulse of one pair: its row (clamped into [0, F)) and fixed-point
+// value x / r * inv_unit (zero when outside the grid or the pass, so that the
+// add is harmless).  u1 >= 1 wherever the row is used, so truncation = floor.
 struct Impulse {
   int row;
   int val;
 };
 
-__device__ __forceinline__ Impulse impulse(const double4 &s, const KernelRec &r, int fbc,
-                                           int F, double ku, double ku0, double nfine,
-                                           float inv_unit) {
-  const Dist d = pair_dist(s.x, s.y, s.z, r.cx, r.cy, r.cz);
-  const double kd = floor(fma(d.r, ku, ku0));  // |kd| < 1e9 (checked on the host)
-  const int pp = (int)kd - fbc;
-  const bool in = kd >= 0.0 && kd < nfine && (unsigned)pp < (unsigned)F;
+__device__ __forceinline__ Impulse impulse(const Lane &l, const KernelRec &r, int F,
+                                           double ku) {
+  const Dist d = pair_dist(l.m2x, l.m2y, l.m2z, r.cx, r.cy, r.cz, l.s2 + r.h);
+  const int p1 = (int)fma(d.r, ku, l.cst);  // |value| < 1e9 (checked on the host)
+  const bool in = (unsigned)(p1 - l.plo) < (unsigned)l.pspan;
   Impulse o;
-  o.row = min(max(pp, 0), F - 1);
-  o.val = in ? (int)rintf(r.amp * d.rinv * inv_unit) : 0;
+  o.row = min(max(p1 - 1, 0), F - 1);
+  o.val = in ? (int)rintf(r.amp * d.rinv * l.inv_unit) : 0;
   return o;
 }
 
@@ -157,6 +171,62 @@ __device__ __forceinline__ void lds_add(int *p, int v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Convolution of kHalf coarse samples c0 .. c0 + kHalf - 1 of the lane's
+// column (fixed point in icol, row stride 64), scaled by `unit`, into
+// out[0 .. kHalf).  Sample c reads rows alpha c + [0, 2K]; the caller only
+// asks for samples whose rows are in the segment.
+constexpr int kHalf = kAssaOut / 2;
+
+__device__ __forceinline__ float uniform_f(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
+// Grid known at compile time: the A (kHalf - 1) + 2 KK + 1 rows are loaded
+// once into registers (immediate LDS offsets), the taps sit in scalar
+// registers.
+template <int A, int KK>
+__device__ __forceinline__ void conv_window(const int *icol, int c0, const float *hqs,
+                                            float unit, float *out) {
+  constexpr int W = A * (kHalf - 1) + 2 * KK + 1;
+  float hv[KK];
+#pragma unroll
+  for (int q = 0; q < KK; ++q) hv[q] = uniform_f(hqs[q]);
+  const int *base = icol + (size_t)(A * c0) * kWave;
+  float z[W];
+#pragma unroll
+  for (int i = 0; i < W; ++i) z[i] = (float)base[i * kWave];
+#pragma unroll
+  for (int u = 0; u < kHalf; ++u) {
+    float v = 0.0f;
+#pragma unroll
+    for (int q = 0; q < KK; ++q) v = fmaf(hv[q], z[A * u + q] - z[A * u + 2 * KK - q], v);
+    out[u] = v * unit;
+  }
+}
+
+// Any grid, nu <= kHalf samples: rows read straight from LDS.
+__device__ __forceinline__ void conv_any(const int *icol, int c0, int nu, int alpha, int K,
+                                         const float *hqs, float unit, float *out) {
+  float acc[kHalf];
+#pragma unroll
+  for (int u = 0; u < kHalf; ++u) acc[u] = 0.0f;
+  const int *base = icol + (size_t)alpha * c0 * kWave;
+  const int ustep = alpha * kWave;
+  for (int q = 0; q < K; ++q) {
+    const float hq = hqs[q];
+    const int *lo = base + q * kWave;
+    const int *hi = base + (2 * K - q) * kWave;
+#pragma unroll
+    for (int u = 0; u < kHalf; ++u)
+      if (u < nu) acc[u] = fmaf(hq, (float)lo[u * ustep] - (float)hi[u * ustep], acc[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < kHalf; ++u) out[u] = acc[u] * unit;
+}
+
+// A, KK > 0: the grid (alpha, K) is fixed at compile time (register-window
+// convolution); A = 0: any grid.
+template <int A, int KK>
 __global__ __launch_bounds__(kAssaWaves * kWave) void assa_forward_kernel(
     const KernelRec *__restrict__ krec, AssaFwdArgs a) {
   extern __shared__ float seg[];  // [F][64]: fine row p of sensor column l at p*64 + l
@@ -191,13 +261,17 @@ __global__ __launch_bounds__(kAssaWaves * kWave) void assa_forward_kernel(
     unit = (float)(bound * 0x1p-30);
     inv_unit = bound > 0.0 ? (float)(0x1p30 / bound) : 0.0f;
   }
+  Lane L;
+  L.m2x = -2.0 * s.x;
+  L.m2y = -2.0 * s.y;
+  L.m2z = -2.0 * s.z;
+  L.s2 = s.w;
+  L.inv_unit = inv_unit;
   float *const col = seg + lane;
   int *const icol = reinterpret_cast<int *>(seg) + lane;
   const int per = (T.count + kAssaWaves - 1) / kAssaWaves;
   const int k0 = T.start + wave * per;
   const int k1 = min(T.start + T.count, k0 + per);
-  const double nfine = (double)a.nfine;
-  const int twoK = 2 * a.K;
 
   // Passes over the shell, Lch coarse samples each (one pass unless the
   // shell's fine rows exceed the LDS budget).  Pass cc needs the impulses of
@@ -207,6 +281,10 @@ __global__ __launch_bounds__(kAssaWaves * kWave) void assa_forward_kernel(
   for (int cc = 0; cc < a.Lc; cc += a.Lch) {
     const int nc = min(a.Lch, a.Lc - cc);
     const int fbc = fb + a.alpha * cc;
+    // fine point k = fbc + p1 - 1 is kept iff 0 <= k < nfine and 0 <= p1 - 1 < F
+    L.cst = a.ku0 - (double)fbc + 1.0;
+    L.plo = max(1, 1 - fbc);
+    L.pspan = max(0, min(a.F + 1, a.nfine - fbc + 1) - L.plo);
     if (cc > 0) __syncthreads();  // the previous pass's flush has read the segment
     {
       float4 *s4 = reinterpret_cast<float4 *>(seg);
@@ -226,45 +304,37 @@ __global__ __launch_bounds__(kAssaWaves * kWave) void assa_forward_kernel(
       KernelRec ra = krec[k0], rb = krec[min(k0 + 1, last)];
       int k = k0;
       for (; k + 1 < k1; k += 2) {
-        const Impulse ia = impulse(s, ra, fbc, a.F, a.ku, a.ku0, nfine, inv_unit);
-        const Impulse ib = impulse(s, rb, fbc, a.F, a.ku, a.ku0, nfine, inv_unit);
+        const Impulse ia = impulse(L, ra, a.F, a.ku);
+        const Impulse ib = impulse(L, rb, a.F, a.ku);
         ra = krec[min(k + 2, last)];
         rb = krec[min(k + 3, last)];
         lds_add(icol + ia.row * kWave, ia.val);
         lds_add(icol + ib.row * kWave, ib.val);
       }
       if (k < k1) {
-        const Impulse ia = impulse(s, ra, fbc, a.F, a.ku, a.ku0, nfine, inv_unit);
+        const Impulse ia = impulse(L, ra, a.F, a.ku);
         lds_add(icol + ia.row * kWave, ia.val);
       }
     }
     __syncthreads();
-    // Fixed point to float, in place: wave w converts rows w, w + 4, ...
-    for (int row = wave; row < a.F; row += kAssaWaves)
-      col[row * kWave] = (float)icol[row * kWave] * unit;
-    __syncthreads();
 
     // 2. Convolution and decimation, 64 coarse samples per round (16 per
-    //    wave).  Round r writes rows [64r, 64r + 64) once every wave has read
-    //    its inputs; later rounds read rows >= alpha (64r + 64), so nothing
-    //    they need is overwritten.
+    //    wave), from the fixed-point rows (converted to float in registers),
+    //    results in float.  Round r writes rows [64r, 64r + 64) once every
+    //    wave has read its inputs; later rounds read rows >= alpha (64r + 64),
+    //    so nothing they need is overwritten.
     for (int c0 = 0; c0 < nc; c0 += kAssaPass) {
       const int cw = c0 + wave * kAssaOut;
       const int nu = min(kAssaOut, nc - cw);  // may be <= 0
       float acc[kAssaOut];
 #pragma unroll
-      for (int u = 0; u < kAssaOut; ++u) acc[u] = 0.0f;
-      if (nu > 0) {
-        const float *base = col + (size_t)a.alpha * cw * kWave;
-        const int ustep = a.alpha * kWave;
-        for (int q = 0; q < a.K; ++q) {
-          const float hq = hqs[q];
-          const float *lo = base + q * kWave;
-          const float *hi = base + (twoK - q) * kWave;
-#pragma unroll
-          for (int u = 0; u < kAssaOut; ++u)
-            if (u < nu) acc[u] = fmaf(hq, lo[u * ustep] - hi[u * ustep], acc[u]);
-        }
+      for (int h = 0; h < 2; ++h) {
+        const int nh = min(kHalf, nu - h * kHalf);  // samples of this half (may be <= 0)
+        if (A > 0 && nh == kHalf)
+          conv_window<(A > 0 ? A : 1), (KK > 0 ? KK : 1)>(icol, cw + h * kHalf, hqs, unit,
+                                                         acc + h * kHalf);
+        else if (nh > 0)
+          conv_any(icol, cw + h * kHalf, nh, a.alpha, a.K, hqs, unit, acc + h * kHalf);
       }
       __syncthreads();
 #pragma unroll
@@ -342,6 +412,7 @@ __global__ __launch_bounds__(BLOCK) void assa_adjoint_kernel(const double4 *__re
                                                             AssaAdjArgs a) {
   extern __shared__ float stage[];  // [S][Fa]
   __shared__ int kbs[kAdjSensorsPerStage];
+  __shared__ double csts[kAdjSensorsPerStage];  // ku0 - kb + |s|^2 folded per sensor
 
   const int64_t logical = xcd_logical(a.nlogical);
   if (logical >= a.nlogical) return;
@@ -353,6 +424,8 @@ __global__ __launch_bounds__(BLOCK) void assa_adjoint_kernel(const double4 *__re
   const int64_t i = T.start + (live ? t : 0);
   const KernelRec r = a.krec[i];
   const int pmax = a.Fa - 1;
+  const double m2x = -2.0 * r.cx, m2y = -2.0 * r.cy, m2z = -2.0 * r.cz;
+  const double c2 = fma(r.cz, r.cz, fma(r.cy, r.cy, r.cx * r.cx));
 
   double acc = 0.0;
   for (int j0 = 0; j0 < a.Nd; j0 += a.S) {
@@ -362,7 +435,9 @@ __global__ __launch_bounds__(BLOCK) void assa_adjoint_kernel(const double4 *__re
       const double4 s = sens[j0 + t];
       const double dx = s.x - T.cx, dy = s.y - T.cy, dz = s.z - T.cz;
       const double R = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
-      kbs[t] = shell_low(R, T.rho, a.ku, a.ku0);
+      const int kb = shell_low(R, T.rho, a.ku, a.ku0);
+      kbs[t] = kb;
+      csts[t] = a.ku0 - (double)kb;
     }
     __syncthreads();
     // Stage the fine-grid shell: one wave per row, lanes along the row;
@@ -380,11 +455,11 @@ __global__ __launch_bounds__(BLOCK) void assa_adjoint_kernel(const double4 *__re
     float p = 0.0f;
     for (int js = 0; js < nsb; ++js) {
       const double4 s = sens[j0 + js];
-      const Dist d = pair_dist(s.x, s.y, s.z, r.cx, r.cy, r.cz);
-      const double kd = floor(fma(d.r, a.ku, a.ku0));
-      // kd - kb is in [1, Fa - 1] by construction of kb and Fa (clamped only
-      // to keep the read in the stage were that ever violated).
-      const int pp = min(max((int)kd - kbs[js], 0), pmax);
+      const Dist d = pair_dist(m2x, m2y, m2z, s.x, s.y, s.z, s.w + c2);
+      // floor(r ku + ku0) - kb is in [1, Fa - 1] by construction of kb and
+      // Fa, so the folded value is >= 1 and truncation is the floor (the clamp
+      // only keeps the read in the stage were that ever violated).
+      const int pp = min(max((int)fma(d.r, a.ku, csts[js]), 0), pmax);
       p = fmaf(stage[js * a.Fa + pp], d.rinv, p);
     }
     acc += (double)p;
@@ -484,7 +559,16 @@ hipError_t launch_assa_forward(const gpair_plan_s *p, const AssaGrid &g, float *
   a.min_dist = p->min_dist;
   for (int q = 0; q < g.K; ++q) a.hq[q] = (float)assa_h(p, g, g.K - q);
   const size_t lds = (size_t)g.F * kWave * sizeof(float);
-  assa_forward_kernel<<<xcd_blocks(a.nlogical), kAssaWaves * kWave, lds, s>>>(ws_krec(p), a);
+  const unsigned int grid = xcd_blocks(a.nlogical);
+  const int block = kAssaWaves * kWave;
+  if (g.alpha == 3 && g.K == 12)
+    assa_forward_kernel<3, 12><<<grid, block, lds, s>>>(ws_krec(p), a);
+  else if (g.alpha == 2 && g.K == 16)
+    assa_forward_kernel<2, 16><<<grid, block, lds, s>>>(ws_krec(p), a);
+  else if (g.alpha == 4 && g.K == 12)
+    assa_forward_kernel<4, 12><<<grid, block, lds, s>>>(ws_krec(p), a);
+  else
+    assa_forward_kernel<0, 0><<<grid, block, lds, s>>>(ws_krec(p), a);
   return hipGetLastError();
 }
 

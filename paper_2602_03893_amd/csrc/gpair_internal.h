@@ -35,6 +35,7 @@ static_assert(sizeof(TileInfo) == 48, "TileInfo layout");
 struct alignas(64) KernelRec {
   double cx, cy, cz;  // centre (m), float64 copy of the caller's float32
   double h;           // n_sigma sigma_k / Delta: window half-width in samples
+                      // (the ASSA forward stores |c|^2 here instead)
   float amp;          // A_k
   float c;            // -log2(e) / (2 sigma_k^2)
   float k1;           // -2 c Delta
@@ -58,7 +59,7 @@ struct WorkspaceLayout {
 };
 
 struct HostTables {
-  std::vector<double> sens;      // [Nd][4]
+  std::vector<double> sens;      // [Nd][4]: x, y, z, |s|^2
   std::vector<double> kgeo;      // [M][4] permuted centres
   std::vector<int32_t> perm;     // [M] permuted index -> caller index
   std::vector<TileInfo> ftiles;  // forward tiles

@@ -238,8 +238,11 @@ gpair_status build_plan(const gpair_geometry *g, gpair_plan_s *p) {
   keys.key.clear();
   keys.key.shrink_to_fit();
   h.sens.assign((size_t)Nd * 4, 0.0);
-  for (int32_t j = 0; j < Nd; ++j)
+  for (int32_t j = 0; j < Nd; ++j) {
     for (int a = 0; a < 3; ++a) h.sens[4 * j + a] = g->sensors[3 * j + a];
+    const double *q = &h.sens[4 * (size_t)j];
+    h.sens[4 * j + 3] = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];  // |s|^2
+  }
 
   // Block level of a tile of T kernels: lattice -> 8^l >= T lattice nodes;
   // point cloud -> a block edge holding about T kernels at the mean density.
