@@ -86,7 +86,7 @@ FLOP_PAIR_ASSA = 13
 PAPER_ASSA_MS = {"forward": 37.41, "adjoint": 4.99}
 
 
-def cpu_baseline_assa(w, centres, sensors, x, sigma, rows=16, stride=64):
+def cpu_baseline_assa(w, centres, sensors, x, sigma, rows=768, stride=2):
     """The float64 ASSA oracle on a bounded sample of the workload: the
     forward for `rows` sensors (all kernels), the back-projection for every
     `stride`-th kernel (all sensors)."""

@@ -51,6 +51,7 @@ namespace {
 constexpr int kAssaWaves = 4;         // waves per forward workgroup (one sensor group)
 constexpr int kAssaOut = 16;          // coarse samples per wave per convolution pass
 constexpr int kAssaPass = kAssaWaves * kAssaOut;
+constexpr int kAssaStageRegs = 16;    // floats per thread of an adjoint stage in flight
 static_assert(kAssaPass == kWave, "one convolution pass covers 64 coarse samples");
 
 __device__ __forceinline__ int64_t xcd_logical(int64_t nlogical) {
@@ -93,6 +94,32 @@ __device__ __forceinline__ Dist pair_dist(double m2x, double m2y, double m2z, do
 // members lie within rho of the tile centre at distance R from the sensor.
 __device__ __forceinline__ int shell_low(double R, double rho, double ku, double ku0) {
   return (int)floor(fma(R - rho, ku, ku0)) - 1;
+}
+
+// Bounding sphere of two consecutive tiles (their kernel ranges are adjacent
+// in the permuted order): the smallest sphere enclosing both spheres, with
+// the same relative margin as the planner's.  Used on the host and on the
+// device, so that the host's segment bound holds for the device's sphere.
+__host__ __device__ inline TileInfo merge_tiles(const TileInfo &a, const TileInfo &b) {
+  TileInfo m = a;
+  m.count = a.count + b.count;
+  const double ex = b.cx - a.cx, ey = b.cy - a.cy, ez = b.cz - a.cz;
+  const double d = sqrt(ex * ex + ey * ey + ez * ez);
+  if (d + b.rho <= a.rho) return m;
+  if (d + a.rho <= b.rho) {
+    m.cx = b.cx;
+    m.cy = b.cy;
+    m.cz = b.cz;
+    m.rho = b.rho;
+    return m;
+  }
+  const double R = 0.5 * (d + a.rho + b.rho);
+  const double f = (R - a.rho) / d;
+  m.cx = a.cx + f * ex;
+  m.cy = a.cy + f * ey;
+  m.cz = a.cz + f * ez;
+  m.rho = R * (1.0 + 1e-12) + 1e-15;
+  return m;
 }
 
 // ---------------------------------------------------------------------------
@@ -401,70 +428,143 @@ struct AssaAdjArgs {
   const int32_t *perm;
   const float *dconv;
   float *out;
-  int64_t nlogical;
+  int64_t nlogical;  // pairs of adjoint tiles
+  int64_t ntiles;    // adjoint tiles
   int32_t Nd, nfine, Fa;
   int32_t S;  // sensors per stage (<= kAdjSensorsPerStage; fewer when Fa is long)
+  uint32_t fdiv;  // ceil(2^32 / Fa)
   double ku, ku0;
 };
 
+// Shell constants of the stage's sensors (threads t < nsb): kb = first fine
+// point of the staged row, cst = ku0 - kb (the snap with the row offset
+// folded in).
+__device__ __forceinline__ void stage_consts(const double4 *sens, const TileInfo &T, int j0,
+                                             int nsb, double ku, double ku0, int *kbs,
+                                             double *csts) {
+  const int t = threadIdx.x;
+  if (t < nsb) {
+    const double4 s = sens[j0 + t];
+    const double dx = s.x - T.cx, dy = s.y - T.cy, dz = s.z - T.cz;
+    const double R = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
+    const int kb = shell_low(R, T.rho, ku, ku0);
+    kbs[t] = kb;
+    csts[t] = ku0 - (double)kb;
+  }
+}
+
+// Element e of a stage (row js = e / Fa of the staged sensors, column
+// c = e - js Fa) is handled by thread e mod BLOCK, in slot e / BLOCK of its
+// register buffer; fdiv = ceil(2^32 / Fa) makes the row a multiply-high
+// (exact for e < 2^16).
+template <int BLOCK>
+__device__ __forceinline__ void stage_load(const float *dconv, int nfine, int Fa, unsigned fdiv,
+                                           int j0, int nsb, const int *kbs,
+                                           float (&buf)[kAssaStageRegs]) {
+  // Branch-free so that all loads issue back to back: an element outside the
+  // stage or the grid loads a valid address (offset 0) and is replaced by 0.
+  // n_sensors * n_fine < 2^31 (checked on the host): 32-bit offsets.
+  const int n = nsb * Fa;
+#pragma unroll
+  for (int k = 0; k < kAssaStageRegs; ++k) {
+    const int e = (int)threadIdx.x + k * BLOCK;
+    const int js = min((int)__umulhi((unsigned)e, fdiv), nsb - 1);
+    const int kk = kbs[js] + (e - js * Fa);
+    const bool ok = e < n && kk >= 0 && kk < nfine;
+    const float v = dconv[ok ? (unsigned)((j0 + js) * nfine + kk) : 0u];
+    buf[k] = ok ? v : 0.0f;
+  }
+}
+
+template <int BLOCK>
+__device__ __forceinline__ void stage_store(float *stage, int n,
+                                            const float (&buf)[kAssaStageRegs]) {
+#pragma unroll
+  for (int k = 0; k < kAssaStageRegs; ++k) {
+    const int e = (int)threadIdx.x + k * BLOCK;
+    if (e < n) stage[e] = buf[k];
+  }
+}
+
+// The stages are software-pipelined: the next stage's rows are loaded into
+// registers before the current stage's pairs are evaluated and written to
+// LDS after them, so their latency overlaps the pair loop; the shell
+// constants are double-buffered.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void assa_adjoint_kernel(const double4 *__restrict__ sens,
                                                             AssaAdjArgs a) {
   extern __shared__ float stage[];  // [S][Fa]
-  __shared__ int kbs[kAdjSensorsPerStage];
-  __shared__ double csts[kAdjSensorsPerStage];  // ku0 - kb + |s|^2 folded per sensor
+  __shared__ int kbs[2][kAdjSensorsPerStage];
+  __shared__ double csts[2][kAdjSensorsPerStage];
 
   const int64_t logical = xcd_logical(a.nlogical);
   if (logical >= a.nlogical) return;
-  const TileInfo T = a.tiles[logical];
+  // Tiles 2b and 2b + 1 (one 8x8x8 block of a lattice for 256-kernel tiles):
+  // thread t takes kernels start + t and start + t + BLOCK.
+  TileInfo T = a.tiles[2 * logical];
+  if (2 * logical + 1 < a.ntiles) T = merge_tiles(T, a.tiles[2 * logical + 1]);
   const int t = threadIdx.x;
-  const int lane = t & (kWave - 1);
-  const int wave = t >> 6;
-  const bool live = t < T.count;
-  const int64_t i = T.start + (live ? t : 0);
-  const KernelRec r = a.krec[i];
+  const bool live0 = t < T.count, live1 = t + BLOCK < T.count;
+  const int64_t i0 = T.start + (live0 ? t : 0), i1 = T.start + (live1 ? t + BLOCK : 0);
+  const KernelRec r0 = a.krec[i0], r1 = a.krec[i1];
   const int pmax = a.Fa - 1;
-  const double m2x = -2.0 * r.cx, m2y = -2.0 * r.cy, m2z = -2.0 * r.cz;
-  const double c2 = fma(r.cz, r.cz, fma(r.cy, r.cy, r.cx * r.cx));
+  const double ax = -2.0 * r0.cx, ay = -2.0 * r0.cy, az = -2.0 * r0.cz;
+  const double ac2 = fma(r0.cz, r0.cz, fma(r0.cy, r0.cy, r0.cx * r0.cx));
+  const double bx = -2.0 * r1.cx, by = -2.0 * r1.cy, bz = -2.0 * r1.cz;
+  const double bc2 = fma(r1.cz, r1.cz, fma(r1.cy, r1.cy, r1.cx * r1.cx));
+  float buf[kAssaStageRegs];
 
-  double acc = 0.0;
+  // Prologue: stage 0 into LDS, constants of stages 0 and 1.
+  int nsb = min(a.S, a.Nd);
+  stage_consts(sens, T, 0, nsb, a.ku, a.ku0, kbs[0], csts[0]);
+  if (a.S < a.Nd)
+    stage_consts(sens, T, a.S, min(a.S, a.Nd - a.S), a.ku, a.ku0, kbs[1], csts[1]);
+  __syncthreads();
+  stage_load<BLOCK>(a.dconv, a.nfine, a.Fa, a.fdiv, 0, nsb, kbs[0], buf);
+  stage_store<BLOCK>(stage, nsb * a.Fa, buf);
+  __syncthreads();
+
+  double acc0 = 0.0, acc1 = 0.0;
+  int cur = 0;
   for (int j0 = 0; j0 < a.Nd; j0 += a.S) {
-    const int nsb = min(a.S, a.Nd - j0);
-    __syncthreads();  // the previous stage has been consumed
-    if (t < nsb) {
-      const double4 s = sens[j0 + t];
-      const double dx = s.x - T.cx, dy = s.y - T.cy, dz = s.z - T.cz;
-      const double R = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
-      const int kb = shell_low(R, T.rho, a.ku, a.ku0);
-      kbs[t] = kb;
-      csts[t] = a.ku0 - (double)kb;
-    }
-    __syncthreads();
-    // Stage the fine-grid shell: one wave per row, lanes along the row;
-    // points outside [0, nfine) read as zero (those pairs are dropped).
-    for (int js = wave; js < nsb; js += BLOCK / kWave) {
-      const float *drow = a.dconv + (int64_t)(j0 + js) * a.nfine;
-      const int kb = kbs[js];
-      for (int c = lane; c < a.Fa; c += kWave) {
-        const int k = kb + c;
-        stage[js * a.Fa + c] = (k >= 0 && k < a.nfine) ? drow[k] : 0.0f;
-      }
-    }
-    __syncthreads();
+    const int j1 = j0 + a.S;
+    const int nsn = j1 < a.Nd ? min(a.S, a.Nd - j1) : 0;  // sensors of the next stage
+    if (nsn > 0)
+      stage_load<BLOCK>(a.dconv, a.nfine, a.Fa, a.fdiv, j1, nsn, kbs[cur ^ 1], buf);
 
-    float p = 0.0f;
+    const double *cst = csts[cur];
+    float p0 = 0.0f, p1 = 0.0f;
     for (int js = 0; js < nsb; ++js) {
       const double4 s = sens[j0 + js];
-      const Dist d = pair_dist(m2x, m2y, m2z, s.x, s.y, s.z, s.w + c2);
+      const double c = cst[js];
+      const Dist d0 = pair_dist(ax, ay, az, s.x, s.y, s.z, s.w + ac2);
+      const Dist d1 = pair_dist(bx, by, bz, s.x, s.y, s.z, s.w + bc2);
       // floor(r ku + ku0) - kb is in [1, Fa - 1] by construction of kb and
-      // Fa, so the folded value is >= 1 and truncation is the floor (the clamp
-      // only keeps the read in the stage were that ever violated).
-      const int pp = min(max((int)fma(d.r, a.ku, csts[js]), 0), pmax);
-      p = fmaf(stage[js * a.Fa + pp], d.rinv, p);
+      // Fa, so the folded value is >= 1 and truncation is the floor; the
+      // unsigned clamp only keeps the read in the stage were that ever
+      // violated.
+      const unsigned q0 = min((unsigned)(int)fma(d0.r, a.ku, c), (unsigned)pmax);
+      const unsigned q1 = min((unsigned)(int)fma(d1.r, a.ku, c), (unsigned)pmax);
+      const float *row = stage + js * a.Fa;
+      p0 = fmaf(row[q0], d0.rinv, p0);
+      p1 = fmaf(row[q1], d1.rinv, p1);
     }
-    acc += (double)p;
+    acc0 += (double)p0;
+    acc1 += (double)p1;
+
+    __syncthreads();  // stage j0 and its constants are consumed
+    if (nsn > 0) {
+      stage_store<BLOCK>(stage, nsn * a.Fa, buf);
+      const int j2 = j1 + a.S;
+      if (j2 < a.Nd)
+        stage_consts(sens, T, j2, min(a.S, a.Nd - j2), a.ku, a.ku0, kbs[cur], csts[cur]);
+    }
+    __syncthreads();
+    cur ^= 1;
+    nsb = nsn;
   }
-  if (live) a.out[a.perm[i]] = (float)acc;
+  if (live0) a.out[a.perm[i0]] = (float)acc0;
+  if (live1) a.out[a.perm[i1]] = (float)acc1;
 }
 
 double max_tile_rho(const std::vector<TileInfo> &tiles) {
@@ -494,7 +594,7 @@ gpair_status assa_grid(const gpair_plan_s *p, double sigma, AssaGrid *g) {
   o.K = o.alpha * o.n_half;
   if (o.K > kAssaMaxK) return GPAIR_ERR_INVALID_ARG;
   const int64_t nfine = (int64_t)o.alpha * p->Nt;
-  if (nfine >= (int64_t(1) << 30)) return GPAIR_ERR_INVALID_ARG;
+  if (nfine * p->Nd >= (int64_t(1) << 31)) return GPAIR_ERR_INVALID_ARG;
   o.n_fine = (int32_t)nfine;
   // Every fine index the kernels form must stay well inside int range.
   double smax = 0.0, cmax = 0.0;
@@ -508,7 +608,16 @@ gpair_status assa_grid(const gpair_plan_s *p, double sigma, AssaGrid *g) {
   const double ku0 = 0.5 - (double)o.alpha * p->t0 / p->dt;
   if (!((smax + cmax) * ku + std::fabs(ku0) + 8.0 * (o.K + 2) < 1e9))
     return GPAIR_ERR_INVALID_ARG;
-  const double rf = max_tile_rho(p->host.ftiles), ra = max_tile_rho(p->host.atiles);
+  const double rf = max_tile_rho(p->host.ftiles);
+  double ra = 0.0;  // the back-projection works on pairs of adjoint tiles
+  {
+    const std::vector<TileInfo> &at = p->host.atiles;
+    for (size_t b = 0; b < at.size(); b += 2) {
+      const TileInfo m = b + 1 < at.size() ? merge_tiles(at[b], at[b + 1]) : at[b];
+      ra = std::max(ra, m.rho);
+    }
+    ra *= 1.0 + 1e-9;  // device rounding of the same formula
+  }
   const double lc = std::ceil(2.0 * rf * p->inv_vdt + 2.0 * nh) + 4.0;
   const double fa = std::ceil(2.0 * o.alpha * ra * p->inv_vdt) + 4.0;
   if (!(lc < 1e6 && fa < 1e6)) return GPAIR_ERR_INVALID_ARG;
@@ -522,7 +631,9 @@ gpair_status assa_grid(const gpair_plan_s *p, double sigma, AssaGrid *g) {
   o.F = o.alpha * (o.Lch - 1) + 2 * o.K + 1;
   // Adjoint: as many sensors per stage as fit, at most kAdjSensorsPerStage.
   o.Fa = (int32_t)fa;
-  o.S = std::min<int64_t>(kAdjSensorsPerStage, kMaxSegmentBytes / (4 * (int64_t)o.Fa));
+  // (and whose elements fit the registers of the software pipeline)
+  o.S = (int32_t)std::min<int64_t>({kAdjSensorsPerStage, kMaxSegmentBytes / (4 * (int64_t)o.Fa),
+                                    (int64_t)kAssaStageRegs * p->adj_tile / o.Fa});
   if (o.S < 1) return GPAIR_ERR_INVALID_ARG;
   *g = o;
   return GPAIR_OK;
@@ -597,11 +708,13 @@ hipError_t launch_assa_adjoint(const gpair_plan_s *p, const AssaGrid &g, const f
   a.perm = ws_perm(p);
   a.dconv = dconv;
   a.out = out;
-  a.nlogical = (int64_t)p->host.atiles.size();
+  a.ntiles = (int64_t)p->host.atiles.size();
+  a.nlogical = (a.ntiles + 1) / 2;
   a.Nd = p->Nd;
   a.nfine = g.n_fine;
   a.Fa = g.Fa;
   a.S = g.S;
+  a.fdiv = (uint32_t)(((uint64_t(1) << 32) + (uint64_t)g.Fa - 1) / (uint64_t)g.Fa);
   a.ku = (double)g.alpha / p->vdt;
   a.ku0 = 0.5 - (double)g.alpha * p->t0 / p->dt;
   const size_t lds = (size_t)g.Fa * g.S * sizeof(float);
