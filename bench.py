@@ -37,9 +37,15 @@ MEASURED_TRAFFIC = {
 }
 
 
-def kernel_source_hash():
+# The same for the ASSA kernels (assa.hip).
+MEASURED_TRAFFIC_ASSA = {
+    "fb549a835c469678": {"assa_forward_kernel": 5.977e9, "assa_adjoint_kernel": 0.851e9},
+}
+
+
+def kernel_source_hash(name="operators.hip"):
     import hashlib
-    path = os.path.join(ROOT, "paper_2602_03893_amd", "csrc", "operators.hip")
+    path = os.path.join(ROOT, "paper_2602_03893_amd", "csrc", name)
     with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
@@ -193,7 +199,9 @@ def bench_assa(args):
         "plan_s": t_plan,
         "roofline": {"bound": "alu", "kernel": "assa_forward_kernel", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None},
+                     "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": MEASURED_TRAFFIC_ASSA.get(kernel_source_hash("assa.hip"), {})
+                                                     .get("assa_forward_kernel")},
     }
     if not args.no_cpu_baseline:
         log("bench --assa: timing the float64 ASSA oracle on a sample (cpu_baseline)")
