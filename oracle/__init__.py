@@ -14,6 +14,11 @@ Contents
                 two-term pressure) and their numerical Poisson-integral checks.
  - ``solvers``  relative residual, power iteration, projected gradient and Adam
                 loops in float64 on top of ``ops``.
+ - ``assa``     the ASSA operators (three stages as defined, and per pair).
+ - ``objective`` the non-negativity parameterisation, the vessel continuity
+                regulariser (value and gradient), the warm-restart schedule and
+                the full reconstruction loop with all three.
+ - ``nn``       the warm-start network's layers and whole forward/backward.
 
 Pins (what each function is checked against, in ``tests/``):
  - ``ops.forward``   numerical Poisson integral, Eq. (pa_wave), by quadrature
@@ -27,5 +32,7 @@ Pins (what each function is checked against, in ``tests/``):
  - ``solvers.pgd``   converges to scipy's NNLS solution (a different algorithm).
  - ``solvers.adam``  matches torch.optim.Adam (a library implementation) step by
                      step on the same gradients.
+ - ``assa``          tests/test_oracle_assa.py; ``objective``
+                     tests/test_oracle_objective.py; ``nn`` tests/test_oracle_nn.py.
 """
 from . import ops, physics, solvers  # noqa: F401
