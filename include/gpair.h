@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define GPAIR_ABI_VERSION 1
+#define GPAIR_ABI_VERSION 2
 
 /* Identical to hipStream_t. */
 typedef struct ihipStream_t *gpair_stream;
@@ -318,6 +318,17 @@ gpair_status gpair_warm_rescale(gpair_plan p, float *A, const float *sigma, cons
  *  a_lo, a_hi    clamp of A after each update (a_lo = 0 gives A >= 0).
  *  check_every   read the residual back to the host every this many
  *                iterations (>= 1); the stop test runs only then.
+ * The rest of the paper's objective (Algorithm 2 in full; all off when zero):
+ *  npc           non-zero: the non-negativity parameterisation x = (z +
+ *                npc_eps)^2 with Adam on the latent z (Adam only; A then
+ *                holds z on entry and x = (z + npc_eps)^2 on return, and
+ *                a_lo / a_hi are not used).
+ *  reg_lambda, reg_beta, reg_eps   the vessel continuity regulariser (see
+ *                gpair_vcr) added to the loss as reg_lambda * R_VCR(x), on the
+ *                kernel lattice grid_nx x grid_ny x grid_nz (caller order, x
+ *                fastest; the product must equal n_kernels).
+ *  lr_min, cawr_T0, cawr_Tmult   cawr_T0 > 0: the learning rate of A (or z)
+ *                follows gpair_cawr_rate(t, lr_min, lr_A, cawr_T0, cawr_Tmult).
  */
 typedef struct gpair_solve_opts {
   int32_t method;
@@ -335,6 +346,17 @@ typedef struct gpair_solve_opts {
   double a_lo;
   double a_hi;
   int32_t check_every;
+  int32_t npc;
+  double npc_eps;
+  double reg_lambda;
+  double reg_beta;
+  double reg_eps;
+  int32_t grid_nx;
+  int32_t grid_ny;
+  int32_t grid_nz;
+  double lr_min;
+  int32_t cawr_T0;
+  int32_t cawr_Tmult;
 } gpair_solve_opts;
 
 /*
@@ -357,10 +379,11 @@ gpair_status gpair_solve_workspace_size(gpair_plan p,
                                         size_t *bytes);
 
 /*
- * Algorithm 2 without its regulariser, non-negativity parameterisation and
- * learning-rate schedule (the data-fidelity loop): from the caller's start,
- * repeat forward -> residual -> adjoint -> update until rho <= tol or
- * max_iters.  One host synchronisation every check_every iterations.
+ * Algorithm 2: from the caller's start, repeat [NPC map ->] forward ->
+ * residual -> adjoint [-> + lambda grad R_VCR -> NPC chain rule] -> update
+ * (with the [CAWR] rate) until rho <= tol or max_iters; the bracketed steps
+ * run when the options enable them.  One host synchronisation every
+ * check_every iterations.
  *  b       device float32 [n_sensors][n_samples]  measured traces.
  *  A       device float32 [n_kernels]  in: start, out: result.
  *  sigma   device float32 [n_kernels]  in/out (updated iff learn_sigma).
@@ -455,6 +478,61 @@ gpair_status gpair_assa_forward(gpair_plan p, const float *x, double sigma, floa
  */
 gpair_status gpair_assa_adjoint(gpair_plan p, double sigma, const float *delta, float *g,
                                 void *work, size_t work_bytes, gpair_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* f2. The paper's full objective: NPC, VCR, CAWR                             */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Non-negativity parameterisation ("Nonnegative parameterization
+ * constraint"): x = (z + eps)^2 elementwise (the paper's eps = 1e-8).
+ *  z, x   device float32 [n]; x may alias z.  Errors: INVALID_ARG, HIP.
+ */
+gpair_status gpair_npc_map(int64_t n, const float *z, double eps, float *x,
+                           gpair_stream stream);
+
+/*
+ * Its chain rule: gz = gx * 2 (z + eps) elementwise.
+ *  z, gx, gz  device float32 [n]; gz may alias gx.  Errors: INVALID_ARG, HIP.
+ */
+gpair_status gpair_npc_grad(int64_t n, const float *z, const float *gx, double eps,
+                            float *gz, gpair_stream stream);
+
+/* Device work bytes of gpair_vcr on an nx x ny x nz volume.  INVALID_ARG. */
+gpair_status gpair_vcr_workspace_size(int32_t nx, int32_t ny, int32_t nz, size_t *bytes);
+
+/*
+ * Vessel continuity regulariser ("Vessel continuity regularization"):
+ *   R_VCR(x) = R_H(x) + beta R_TV(x),
+ *   R_H  = sum_i sqrt( sum_{p,q in {x,y,z}} (D_pq x_i)^2 + eps ),
+ *   R_TV = sum_i sqrt( sum_{d} (D_d x_i)^2 + eps ),
+ * on a volume stored [nz][ny][nx] (x fastest: the caller's kernel order of a
+ * lattice plan), unit spacing, with D_d x_i = x[i+e_d] - x[i],
+ * D_pp x_i = x[i+e_p] - 2 x[i] + x[i-e_p], D_pq x_i = x[i+e_p+e_q] - x[i+e_p]
+ * - x[i+e_q] + x[i] (p != q; D_pq = D_qp, so each mixed term counts twice) and
+ * every difference whose stencil leaves the volume taken as 0.
+ *  x      device float32 [nz][ny][nx].
+ *  grad   device float32 [nz][ny][nx] or NULL: grad += lambda * dR_VCR/dx.
+ *  value  device float64 [1] or NULL: R_VCR(x), summed in a fixed order.
+ *  work   device, >= gpair_vcr_workspace_size bytes, 256-byte aligned.
+ * Differences and norms are float64, the normalised terms float32.
+ * Errors: INVALID_ARG, WORKSPACE, HIP.
+ */
+gpair_status gpair_vcr(int32_t nx, int32_t ny, int32_t nz, const float *x, double beta,
+                       double eps, double lambda, float *grad, double *value, void *work,
+                       size_t work_bytes, gpair_stream stream);
+
+/*
+ * Cosine annealing with warm restarts ("Optimization formulation and
+ * algorithm"), host only: eta_t = eta_min + (eta_max - eta_min)(1 + cos(pi
+ * T_cur / T_i)) / 2 for iteration t >= 0, where period i has length
+ * T0 * Tmult^i and T_cur counts iterations since the period began (the cited
+ * SGDR schedule; for Tmult = 1 exactly the printed formula with
+ * T_cur = t mod T0).  Errors: INVALID_ARG (t < 0, T0 < 1, Tmult < 1,
+ * non-finite rates).
+ */
+gpair_status gpair_cawr_rate(int64_t t, double eta_min, double eta_max, int64_t T0,
+                             int32_t Tmult, double *rate);
 
 /* ------------------------------------------------------------------------ */
 /* Kernel timing (measurement support)                                        */

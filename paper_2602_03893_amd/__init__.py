@@ -12,6 +12,10 @@ _LAZY = {
     "Plan": ("api", "Plan"),
     "pgd_update": ("api", "pgd_update"),
     "adam_update": ("api", "adam_update"),
+    "npc_map": ("api", "npc_map"),
+    "npc_grad": ("api", "npc_grad"),
+    "vcr": ("api", "vcr"),
+    "cawr_rate": ("api", "cawr_rate"),
     "GpairError": ("_lib", "GpairError"),
     "GpairForward": ("autograd", "GpairForward"),
     "gpair_forward": ("autograd", "gpair_forward"),

@@ -71,7 +71,10 @@ class SolveOpts(ctypes.Structure):
                 ("lr_A", c_dbl), ("lr_sigma", c_dbl), ("beta1", c_dbl), ("beta2", c_dbl),
                 ("eps", c_dbl), ("learn_sigma", c_i32), ("sigma_lo", c_dbl),
                 ("sigma_hi", c_dbl), ("a_lo", c_dbl), ("a_hi", c_dbl),
-                ("check_every", c_i32)]
+                ("check_every", c_i32), ("npc", c_i32), ("npc_eps", c_dbl),
+                ("reg_lambda", c_dbl), ("reg_beta", c_dbl), ("reg_eps", c_dbl),
+                ("grid_nx", c_i32), ("grid_ny", c_i32), ("grid_nz", c_i32),
+                ("lr_min", c_dbl), ("cawr_T0", c_i32), ("cawr_Tmult", c_i32)]
 
 
 class SolveReport(ctypes.Structure):
@@ -88,6 +91,10 @@ def _proto(name, restype, argtypes):
 
 gpair_status_string = _proto("gpair_status_string", ctypes.c_char_p, [c_i32])
 gpair_abi_version = _proto("gpair_abi_version", ctypes.c_int, [])
+ABI_VERSION = 2  # GPAIR_ABI_VERSION of include/gpair.h this binding is written for
+if gpair_abi_version() != ABI_VERSION:
+    raise ImportError(f"{LIB_PATH} has ABI version {gpair_abi_version()}, this binding "
+                      f"expects {ABI_VERSION}: rebuild the library")
 gpair_plan_create = _proto("gpair_plan_create", c_i32,
                            [ctypes.POINTER(Geometry), ctypes.POINTER(c_vp)])
 gpair_plan_workspace_size = _proto("gpair_plan_workspace_size", c_i32,
@@ -131,6 +138,14 @@ gpair_assa_workspace_size = _proto("gpair_assa_workspace_size", c_i32,
 gpair_assa_forward = _proto("gpair_assa_forward", c_i32, [c_vp, c_vp, c_dbl, c_vp, c_vp])
 gpair_assa_adjoint = _proto("gpair_assa_adjoint", c_i32,
                             [c_vp, c_dbl, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp])
+gpair_npc_map = _proto("gpair_npc_map", c_i32, [c_i64, c_vp, c_dbl, c_vp, c_vp])
+gpair_npc_grad = _proto("gpair_npc_grad", c_i32, [c_i64, c_vp, c_vp, c_dbl, c_vp, c_vp])
+gpair_vcr_workspace_size = _proto("gpair_vcr_workspace_size", c_i32,
+                                  [c_i32, c_i32, c_i32, ctypes.POINTER(ctypes.c_size_t)])
+gpair_vcr = _proto("gpair_vcr", c_i32, [c_i32, c_i32, c_i32, c_vp, c_dbl, c_dbl, c_dbl, c_vp,
+                                        c_vp, c_vp, ctypes.c_size_t, c_vp])
+gpair_cawr_rate = _proto("gpair_cawr_rate", c_i32,
+                         [c_i64, c_dbl, c_dbl, c_i64, c_i32, ctypes.POINTER(c_dbl)])
 gpair_plan_set_timing = _proto("gpair_plan_set_timing", c_i32, [c_vp, ctypes.c_int])
 gpair_plan_kernel_times = _proto("gpair_plan_kernel_times", c_i32,
                                  [c_vp, ctypes.c_int, c_fp, c_i32, ctypes.POINTER(c_i32)])

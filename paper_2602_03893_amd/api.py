@@ -231,8 +231,12 @@ class Plan:
     def solve(self, b, A, sigma, method="adam", max_iters=100, tol=0.0, step=0.0,
               lr_A=1e-2, lr_sigma=0.0, beta1=0.9, beta2=0.999, eps=1e-8,
               learn_sigma=False, sigma_lo=None, sigma_hi=None, a_lo=0.0,
-              a_hi=float("inf"), check_every=1):
-        """Run gpair_solve in place on A (and sigma).  Returns a dict report."""
+              a_hi=float("inf"), check_every=1, npc=False, npc_eps=1e-8, reg_lambda=0.0,
+              reg_beta=1.0, reg_eps=1e-8, grid=None, lr_min=0.0, cawr_T0=0, cawr_Tmult=1):
+        """Run gpair_solve in place on A (and sigma).  Returns a dict report.
+        npc: A holds the latent z on entry and x = (z + npc_eps)^2 on return.
+        reg_lambda != 0 needs grid = (nx, ny, nz) of the kernel lattice.
+        cawr_T0 > 0: learning rate of A (or z) by the warm-restart schedule."""
         o = _lib.SolveOpts()
         o.method = {"pgd": _lib.SOLVE_PGD, "adam": _lib.SOLVE_ADAM}[method]
         o.max_iters = int(max_iters)
@@ -246,6 +250,11 @@ class Plan:
         o.sigma_hi = float(sigma_hi if sigma_hi is not None else self.sigma_max)
         o.a_lo, o.a_hi = float(a_lo), float(a_hi)
         o.check_every = int(check_every)
+        o.npc = 1 if npc else 0
+        o.npc_eps = float(npc_eps)
+        o.reg_lambda, o.reg_beta, o.reg_eps = float(reg_lambda), float(reg_beta), float(reg_eps)
+        o.grid_nx, o.grid_ny, o.grid_nz = (int(v) for v in (grid or (0, 0, 0)))
+        o.lr_min, o.cawr_T0, o.cawr_Tmult = float(lr_min), int(cawr_T0), int(cawr_Tmult)
         nbytes = ctypes.c_size_t()
         check(_lib.gpair_solve_workspace_size(self._h, ctypes.byref(o), ctypes.byref(nbytes)),
               "gpair_solve_workspace_size")
@@ -282,4 +291,54 @@ def adam_update(x, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, grad_scale=
     return x
 
 
-__all__ = ["Plan", "pgd_update", "adam_update", "GpairError"]
+def npc_map(z, eps=1e-8, out=None):
+    """x = (z + eps)^2 (float32 device tensors; out may be z)."""
+    n = z.numel()
+    out = torch.empty_like(z) if out is None else out
+    check(_lib.gpair_npc_map(n, _dev(z, "z", n), float(eps), _dev(out, "x", n), _stream()),
+          "gpair_npc_map")
+    return out
+
+
+def npc_grad(z, gx, eps=1e-8, out=None):
+    """gz = gx * 2 (z + eps) (out may be gx)."""
+    n = z.numel()
+    out = torch.empty_like(gx) if out is None else out
+    check(_lib.gpair_npc_grad(n, _dev(z, "z", n), _dev(gx, "gx", n), float(eps),
+                              _dev(out, "gz", n), _stream()), "gpair_npc_grad")
+    return out
+
+
+def vcr(x, beta, eps=1e-8, lam=1.0, grad=None, want_value=True, work=None):
+    """The vessel continuity regulariser of a float32 volume x of shape
+    (nz, ny, nx): returns (value as a float64 device tensor or None, grad), with
+    grad += lam * dR/dx when `grad` is given (a zero tensor is made when
+    grad is None and lam != 0)."""
+    if x.dim() != 3:
+        raise ValueError("x: expected a (nz, ny, nx) volume")
+    nz, ny, nx = x.shape
+    nbytes = ctypes.c_size_t()
+    check(_lib.gpair_vcr_workspace_size(nx, ny, nz, ctypes.byref(nbytes)),
+          "gpair_vcr_workspace_size")
+    if work is None:
+        work = torch.empty(int(nbytes.value), dtype=torch.uint8, device=x.device)
+    if grad is None and lam != 0.0:
+        grad = torch.zeros_like(x)
+    value = torch.empty(1, dtype=torch.float64, device=x.device) if want_value else None
+    check(_lib.gpair_vcr(nx, ny, nz, _dev(x, "x", x.numel()), float(beta), float(eps),
+                         float(lam), _dev(grad, "grad", x.numel()) if grad is not None else None,
+                         _dev(value, "value", 1, dtype=torch.float64) if value is not None
+                         else None, _dev(work, "work", dtype=torch.uint8), work.numel(),
+                         _stream()), "gpair_vcr")
+    return value, grad
+
+
+def cawr_rate(t, eta_min, eta_max, T0, Tmult=1):
+    r = ctypes.c_double()
+    check(_lib.gpair_cawr_rate(int(t), float(eta_min), float(eta_max), int(T0), int(Tmult),
+                               ctypes.byref(r)), "gpair_cawr_rate")
+    return r.value
+
+
+__all__ = ["Plan", "pgd_update", "adam_update", "npc_map", "npc_grad", "vcr", "cawr_rate",
+           "GpairError"]

@@ -234,6 +234,60 @@ gpair_status gpair_assa_adjoint(gpair_plan p, double sigma, const float *delta, 
   return hip_status(e);
 }
 
+gpair_status gpair_npc_map(int64_t n, const float *z, double eps, float *x,
+                           gpair_stream stream) {
+  if (n < 0 || (n > 0 && (!z || !x)) || !std::isfinite(eps)) return GPAIR_ERR_INVALID_ARG;
+  if (n == 0) return GPAIR_OK;
+  return hip_status(launch_npc_map(n, z, (float)eps, x, (hipStream_t)stream));
+}
+
+gpair_status gpair_npc_grad(int64_t n, const float *z, const float *gx, double eps, float *gz,
+                            gpair_stream stream) {
+  if (n < 0 || (n > 0 && (!z || !gx || !gz)) || !std::isfinite(eps))
+    return GPAIR_ERR_INVALID_ARG;
+  if (n == 0) return GPAIR_OK;
+  return hip_status(launch_npc_grad(n, z, gx, (float)eps, gz, (hipStream_t)stream));
+}
+
+static bool vcr_dims_ok(int32_t nx, int32_t ny, int32_t nz) {
+  return nx >= 1 && ny >= 1 && nz >= 1 && (int64_t)nx * ny * nz <= (int64_t(1) << 31) / 16;
+}
+
+gpair_status gpair_vcr_workspace_size(int32_t nx, int32_t ny, int32_t nz, size_t *bytes) {
+  if (!bytes || !vcr_dims_ok(nx, ny, nz)) return GPAIR_ERR_INVALID_ARG;
+  *bytes = vcr_work_bytes(nx, ny, nz);
+  return GPAIR_OK;
+}
+
+gpair_status gpair_vcr(int32_t nx, int32_t ny, int32_t nz, const float *x, double beta,
+                       double eps, double lambda, float *grad, double *value, void *work,
+                       size_t work_bytes, gpair_stream stream) {
+  if (!vcr_dims_ok(nx, ny, nz) || !x || !std::isfinite(beta) || !(eps >= 0.0) ||
+      !std::isfinite(eps) || !std::isfinite(lambda))
+    return GPAIR_ERR_INVALID_ARG;
+  if (!work || work_bytes < vcr_work_bytes(nx, ny, nz) || ((uintptr_t)work & 255u))
+    return GPAIR_ERR_WORKSPACE;
+  if (!grad && !value) return GPAIR_OK;
+  return hip_status(
+      launch_vcr(nx, ny, nz, x, beta, eps, lambda, grad, value, work, (hipStream_t)stream));
+}
+
+gpair_status gpair_cawr_rate(int64_t t, double eta_min, double eta_max, int64_t T0,
+                             int32_t Tmult, double *rate) {
+  if (!rate || t < 0 || T0 < 1 || Tmult < 1 || !std::isfinite(eta_min) ||
+      !std::isfinite(eta_max))
+    return GPAIR_ERR_INVALID_ARG;
+  int64_t start = 0, period = T0;
+  while (t >= start + period) {
+    start += period;
+    if (period > (int64_t(1) << 40) / Tmult) break;  // t lies in this (huge) period
+    period *= Tmult;
+  }
+  const double tc = (double)(t - start), ti = (double)period;
+  *rate = eta_min + 0.5 * (eta_max - eta_min) * (1.0 + std::cos(M_PI * tc / ti));
+  return GPAIR_OK;
+}
+
 gpair_status gpair_sigma_violations(gpair_plan p, int64_t *count, gpair_stream stream) {
   if (!bound(p) || !count) return GPAIR_ERR_INVALID_ARG;
   unsigned long long v = 0;

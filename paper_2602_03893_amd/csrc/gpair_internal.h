@@ -140,6 +140,15 @@ hipError_t launch_assa_dconv(const gpair_plan_s *p, const AssaGrid &g, const flo
 hipError_t launch_assa_adjoint(const gpair_plan_s *p, const AssaGrid &g, const float *dconv,
                                float *out, hipStream_t s);
 
+// The full objective (objective.hip).
+hipError_t launch_npc_map(int64_t n, const float *z, float eps, float *x, hipStream_t s);
+hipError_t launch_npc_grad(int64_t n, const float *z, const float *gx, float eps, float *gz,
+                           hipStream_t s);
+size_t vcr_work_bytes(int32_t nx, int32_t ny, int32_t nz);
+hipError_t launch_vcr(int32_t nx, int32_t ny, int32_t nz, const float *x, double beta,
+                      double eps, double lambda, float *grad, double *value, void *work,
+                      hipStream_t s);
+
 // Workspace pointers of a bound plan.
 inline double *ws_sens(const gpair_plan_s *p) { return (double *)(p->ws + p->lay.sens); }
 inline int32_t *ws_perm(const gpair_plan_s *p) { return (int32_t *)(p->ws + p->lay.perm); }

@@ -12,7 +12,7 @@ using namespace gpair;
 namespace {
 
 struct SolveLayout {
-  size_t y, gA, gS, mA, vA, mS, vS, norms, total;
+  size_t y, gA, gS, mA, vA, mS, vS, norms, z, vcr, total;
 };
 
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -31,6 +31,10 @@ SolveLayout solve_layout(const gpair_plan_s *p, const gpair_solve_opts *o) {
   l.mS = off;    off = a256(off + (sig ? M * 4 : 0));
   l.vS = off;    off = a256(off + (sig ? M * 4 : 0));
   l.norms = off; off = a256(off + 2 * sizeof(double));
+  l.z = off;     off = a256(off + (o->npc ? M * 4 : 0));
+  l.vcr = off;
+  off = a256(off + (o->reg_lambda != 0.0 ? vcr_work_bytes(o->grid_nx, o->grid_ny, o->grid_nz)
+                                         : 0));
   l.total = off;
   return l;
 }
@@ -42,6 +46,17 @@ bool valid_opts(const gpair_plan_s *p, const gpair_solve_opts *o) {
   if (!(o->tol >= 0.0) || std::isnan(o->a_lo) || std::isnan(o->a_hi) || o->a_lo > o->a_hi)
     return false;
   if (o->method == GPAIR_SOLVE_PGD && !std::isfinite(o->step)) return false;
+  if (o->npc && (o->method != GPAIR_SOLVE_ADAM || !std::isfinite(o->npc_eps))) return false;
+  if (!std::isfinite(o->reg_lambda)) return false;
+  if (o->reg_lambda != 0.0) {
+    if (!std::isfinite(o->reg_beta) || !(o->reg_eps >= 0.0) || !std::isfinite(o->reg_eps))
+      return false;
+    if (o->grid_nx < 1 || o->grid_ny < 1 || o->grid_nz < 1 ||
+        (int64_t)o->grid_nx * o->grid_ny * o->grid_nz != p->M)
+      return false;
+  }
+  if (o->cawr_T0 < 0 || (o->cawr_T0 > 0 && (o->cawr_Tmult < 1 || !std::isfinite(o->lr_min))))
+    return false;
   if (o->method == GPAIR_SOLVE_ADAM) {
     if (!std::isfinite(o->lr_A) || !(o->beta1 >= 0 && o->beta1 < 1) ||
         !(o->beta2 >= 0 && o->beta2 < 1) || !(o->eps >= 0))
@@ -93,8 +108,14 @@ gpair_status gpair_solve(gpair_plan p, const float *b, float *A, float *sigma,
   r->rel_residual = -1.0;
   r->seconds = 0.0;
 
+  const bool npc = o->npc != 0;
+  const bool reg = o->reg_lambda != 0.0;
+  float *z = npc ? (float *)(ws + L.z) : nullptr;
+  const float npc_eps = (float)o->npc_eps;
   hipError_t e = hipSuccess;
-  if (adam) {
+  // NPC: the latent starts from the caller's A; A then holds x = phi(z).
+  if (npc) e = hipMemcpyAsync(z, A, (size_t)p->M * 4, hipMemcpyDeviceToDevice, s);
+  if (adam && e == hipSuccess) {
     e = launch_fill((float *)(ws + L.mA), M, 0.0f, s);
     if (e == hipSuccess) e = launch_fill((float *)(ws + L.vA), M, 0.0f, s);
     if (sig && e == hipSuccess) e = launch_fill((float *)(ws + L.mS), M, 0.0f, s);
@@ -126,6 +147,7 @@ gpair_status gpair_solve(gpair_plan p, const float *b, float *A, float *sigma,
   bool converged = false;
   double rho = -1.0;
   for (; it < o->max_iters; ++it) {
+    if (npc && launch_npc_map(M, z, npc_eps, A, s) != hipSuccess) return GPAIR_ERR_HIP;
     st = gpair_forward(p, A, sigma, y, stream);
     if (st != GPAIR_OK) return st;
     if (launch_residual(p, y, b, scale, y, norms, s) != hipSuccess) return GPAIR_ERR_HIP;
@@ -143,10 +165,26 @@ gpair_status gpair_solve(gpair_plan p, const float *b, float *A, float *sigma,
     }
     st = gpair_adjoint(p, A, sigma, y, gA, gS, stream);
     if (st != GPAIR_OK) return st;
-    if (adam) {
-      e = launch_adam(M, A, gA, (float *)(ws + L.mA), (float *)(ws + L.vA), 1.0f,
-                      (float)o->lr_A, (float)o->beta1, (float)o->beta2, (float)o->eps, it + 1,
-                      a_lo, a_hi, s);
+    if (reg && launch_vcr(o->grid_nx, o->grid_ny, o->grid_nz, A, o->reg_beta, o->reg_eps,
+                          o->reg_lambda, gA, nullptr, ws + L.vcr, s) != hipSuccess)
+      return GPAIR_ERR_HIP;
+    double lr = o->lr_A;
+    if (o->cawr_T0 > 0 &&
+        gpair_cawr_rate(it, o->lr_min, o->lr_A, o->cawr_T0, o->cawr_Tmult, &lr) != GPAIR_OK)
+      return GPAIR_ERR_INVALID_ARG;
+    if (npc) {
+      e = launch_npc_grad(M, z, gA, npc_eps, gA, s);
+      if (e == hipSuccess)
+        e = launch_adam(M, z, gA, (float *)(ws + L.mA), (float *)(ws + L.vA), 1.0f, (float)lr,
+                        (float)o->beta1, (float)o->beta2, (float)o->eps, it + 1, -INFINITY,
+                        INFINITY, s);
+      if (e == hipSuccess && sig)
+        e = launch_adam(M, sigma, gS, (float *)(ws + L.mS), (float *)(ws + L.vS), 1.0f,
+                        (float)o->lr_sigma, (float)o->beta1, (float)o->beta2, (float)o->eps,
+                        it + 1, (float)o->sigma_lo, (float)o->sigma_hi, s);
+    } else if (adam) {
+      e = launch_adam(M, A, gA, (float *)(ws + L.mA), (float *)(ws + L.vA), 1.0f, (float)lr,
+                      (float)o->beta1, (float)o->beta2, (float)o->eps, it + 1, a_lo, a_hi, s);
       if (e == hipSuccess && sig)
         e = launch_adam(M, sigma, gS, (float *)(ws + L.mS), (float *)(ws + L.vS), 1.0f,
                         (float)o->lr_sigma, (float)o->beta1, (float)o->beta2, (float)o->eps,
@@ -156,6 +194,7 @@ gpair_status gpair_solve(gpair_plan p, const float *b, float *A, float *sigma,
     }
     if (e != hipSuccess) return GPAIR_ERR_HIP;
   }
+  if (npc && launch_npc_map(M, z, npc_eps, A, s) != hipSuccess) return GPAIR_ERR_HIP;
   if (!converged) {
     st = gpair_forward(p, A, sigma, y, stream);
     if (st != GPAIR_OK) return st;

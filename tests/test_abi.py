@@ -33,7 +33,7 @@ def test_library_exports_every_header_function():
     from paper_2602_03893_amd import _lib
     missing = [n for n in header_functions() if not hasattr(_lib.lib, n)]
     assert not missing, missing
-    assert _lib.gpair_abi_version() == 1
+    assert _lib.gpair_abi_version() == _lib.ABI_VERSION == 2
 
 
 def test_status_strings():

@@ -90,3 +90,17 @@ def test_sigma_checks(toy):
     assert _lib.gpair_assa_workspace_size(h, 0.0, ctypes.byref(n)) == -6
     # an unbound plan has no workspace: the operators refuse it
     assert _lib.gpair_assa_forward(h, None, w.sigma, None, None) == -1
+
+
+def test_cawr_rate_matches_the_oracle():
+    """gpair_cawr_rate (host code of the library) against the oracle's schedule."""
+    from oracle import objective as J
+    for T0, Tm in ((10, 1), (7, 2), (3, 3)):
+        for t in range(0, 200, 3):
+            r = ctypes.c_double()
+            assert _lib.gpair_cawr_rate(t, 1e-4, 3e-2, T0, Tm, ctypes.byref(r)) == 0
+            assert r.value == pytest.approx(J.cawr(t, 1e-4, 3e-2, T0, Tm), rel=1e-14)
+    r = ctypes.c_double()
+    assert _lib.gpair_cawr_rate(-1, 0.0, 1.0, 5, 1, ctypes.byref(r)) == -1
+    assert _lib.gpair_cawr_rate(0, 0.0, 1.0, 0, 1, ctypes.byref(r)) == -1
+    assert _lib.gpair_cawr_rate(0, 0.0, 1.0, 5, 0, ctypes.byref(r)) == -1
