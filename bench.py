@@ -118,6 +118,78 @@ def cpu_baseline_assa(w, centres, sensors, x, sigma, rows=768, stride=2):
                        f"({t_adj:.2f} s); rate = pairs / time")}
 
 
+# Full objective (--objective): the regulariser's weight and balance, the
+# warm-restart schedule.  The paper gives no values; these make the VCR term a
+# few percent of the normalised data term at the start and restart every 16
+# steps.
+OBJ_LAMBDA, OBJ_BETA, OBJ_EPS = 1e-7, 0.5, 1e-8
+OBJ_T0, OBJ_TMULT, OBJ_LR_MIN = 16, 2, 1e-4
+# VCR traffic per voxel (algorithmic): terms pass reads x (4 B) and writes nine
+# float32 terms (36 B); gradient pass reads the nine terms (36 B) and reads and
+# writes the gradient (8 B).
+VCR_BYTES_PER_VOXEL = 4 + 36 + 36 + 8
+PEAK_HBM_GBS = 8000.0
+
+
+class Objective:
+    """NPC + VCR + CAWR around a step's operators (Algorithm 2), timing the
+    regulariser with events on the library's stream."""
+
+    def __init__(self, w, dev):
+        import torch
+        from paper_2602_03893_amd import vcr
+        self.w = w
+        self.shape = (w.grid[2], w.grid[1], w.grid[0])
+        self.z = torch.zeros(w.n_kernels, dtype=torch.float32, device=dev)
+        nbytes = ctypes_vcr_bytes(*w.grid)
+        self.work = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.vcr = vcr
+        self.ev = []
+
+    def x_from_z(self, x):
+        from paper_2602_03893_amd import npc_map
+        npc_map(self.z, out=x)
+
+    def add_reg_and_chain(self, x, gx):
+        import torch
+        from paper_2602_03893_amd import npc_grad
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        self.vcr(x.view(self.shape), OBJ_BETA, OBJ_EPS, OBJ_LAMBDA, grad=gx.view(self.shape),
+                 want_value=False, work=self.work)
+        e1.record()
+        self.ev.append((e0, e1))
+        npc_grad(self.z, gx, out=gx)
+
+    def lr(self, t, lr_max):
+        from paper_2602_03893_amd import cawr_rate
+        return cawr_rate(t - 1, OBJ_LR_MIN, lr_max, OBJ_T0, OBJ_TMULT)
+
+    def vcr_ms(self):
+        import numpy as np
+        import torch
+        torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(b) for a, b in self.ev])) if self.ev else None
+
+
+def ctypes_vcr_bytes(nx, ny, nz):
+    import ctypes
+    from paper_2602_03893_amd import _lib
+    n = ctypes.c_size_t()
+    _lib.check(_lib.gpair_vcr_workspace_size(nx, ny, nz, ctypes.byref(n)),
+               "gpair_vcr_workspace_size")
+    return int(n.value)
+
+
+def objective_fields(obj, w):
+    t = obj.vcr_ms()
+    gbs = VCR_BYTES_PER_VOXEL * w.n_kernels / (t * 1e-3) / 1e9
+    return {"objective": {"npc_eps": 1e-8, "vcr_lambda": OBJ_LAMBDA, "vcr_beta": OBJ_BETA,
+                          "vcr_eps": OBJ_EPS, "cawr": {"T0": OBJ_T0, "Tmult": OBJ_TMULT,
+                                                       "lr_min": OBJ_LR_MIN},
+                          "vcr_ms": t, "vcr_GBs": gbs, "vcr_hbm_frac": gbs / PEAK_HBM_GBS}}
+
+
 def bench_assa(args):
     """Paper-scale IR step with the ASSA operators (one shared sigma, the
     paper's own discretisation): forward -> residual -> back-projection ->
@@ -147,13 +219,20 @@ def bench_assa(args):
     work = torch.empty(plan.assa_workspace_bytes(sig), dtype=torch.uint8, device=dev)
     scale = 1.0 / float(torch.sum(b.double() ** 2))
     state = {"t": 0}
+    obj = Objective(w, dev) if args.objective else None
 
     def step():
         state["t"] += 1
+        if obj:
+            obj.x_from_z(A)
         plan.assa_forward(A, sig, out=y)
         plan.residual(y, b, scale=scale, delta=y)
         plan.assa_adjoint(sig, y, out=gA, work=work)
-        adam_update(A, gA, mA, vA, state["t"], 1e-2, lo=0.0)
+        if obj:
+            obj.add_reg_and_chain(A, gA)
+            adam_update(obj.z, gA, mA, vA, state["t"], obj.lr(state["t"], 1e-2))
+        else:
+            adam_update(A, gA, mA, vA, state["t"], 1e-2, lo=0.0)
 
     for _ in range(args.warmup):
         step()
@@ -176,7 +255,8 @@ def bench_assa(args):
     log(f"bench --assa: {ms_step:.2f} ms/step, forward kernel {f_ms:.2f} ms, back-projection "
         f"kernel {a_ms:.2f} ms, {value:.1f} G-evals/s")
     out = {
-        "metric": "fwd+adjoint G-evals/s (paper-scale IR step, ASSA operators)",
+        "metric": ("fwd+adjoint G-evals/s (paper-scale IR step, ASSA operators"
+                   + (", NPC + VCR + CAWR)" if obj else ")")),
         "value": value,
         "unit": "G-evals/s",
         "n_gpus": 1,
@@ -203,6 +283,8 @@ def bench_assa(args):
                      "traffic": MEASURED_TRAFFIC_ASSA.get(kernel_source_hash("assa.hip"), {})
                                                      .get("assa_forward_kernel")},
     }
+    if obj:
+        out.update(objective_fields(obj, w))
     if not args.no_cpu_baseline:
         log("bench --assa: timing the float64 ASSA oracle on a sample (cpu_baseline)")
         out["cpu_baseline"] = cpu_baseline_assa(w, centres, sensors, A_true_h, sig)
@@ -334,6 +416,9 @@ def main():
                     help="benchmark the warm-start U-Net training step instead")
     ap.add_argument("--assa", action="store_true",
                     help="benchmark the IR step with the ASSA operators (shared sigma)")
+    ap.add_argument("--objective", action="store_true",
+                    help="the step of Algorithm 2 in full: NPC latent, VCR regulariser, "
+                         "warm-restart learning rate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 256 MiB device buffer 3 times (scale reference "
                          "for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -395,13 +480,20 @@ def main():
     lr_A, lr_S = 1e-2, 1e-3 * sig0
     s_lo, s_hi = 0.5 * sig0, w.smax
     state = {"t": 0}
+    obj = Objective(w, dev) if args.objective else None
 
     def step():
         state["t"] += 1
+        if obj:
+            obj.x_from_z(A)
         plan.forward(A, sigma, out=y)
         plan.residual(y, b, scale=scale, delta=y)
         plan.adjoint(A, sigma, y, want_sigma=True, out_A=gA, out_sigma=gS)
-        adam_update(A, gA, mA, vA, state["t"], lr_A, lo=0.0)
+        if obj:
+            obj.add_reg_and_chain(A, gA)
+            adam_update(obj.z, gA, mA, vA, state["t"], obj.lr(state["t"], lr_A))
+        else:
+            adam_update(A, gA, mA, vA, state["t"], lr_A, lo=0.0)
         adam_update(sigma, gS, mS, vS, state["t"], lr_S, lo=s_lo, hi=s_hi)
 
     for _ in range(args.warmup):
@@ -436,7 +528,8 @@ def main():
         f"{t_adj:.2f} ms, {value:.1f} G-evals/s")
 
     out = {
-        "metric": "fwd+adjoint G-evals/s (paper-scale differentiable IR step)",
+        "metric": ("fwd+adjoint G-evals/s (paper-scale differentiable IR step"
+                   + (", NPC + VCR + CAWR)" if obj else ")")),
         "value": value,
         "unit": "G-evals/s",
         "n_gpus": 1,
@@ -462,6 +555,8 @@ def main():
                      "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": MEASURED_TRAFFIC.get(kernel_source_hash(), {}).get(dom)},
     }
+    if obj:
+        out.update(objective_fields(obj, w))
     if not args.no_cpu_baseline:
         log("bench: timing the float64 oracle on a sample (cpu_baseline)")
         out["cpu_baseline"] = cpu_baseline(w, centres, sensors, A_true_h, sig0)
