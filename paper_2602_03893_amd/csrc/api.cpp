@@ -85,17 +85,21 @@ gpair_status gpair_plan_bind_workspace(gpair_plan p, void *workspace, size_t wor
   };
   up(p->lay.sens, h.sens.data(), h.sens.size() * sizeof(double));
   // Kernel records: centres now, coefficients on every operator call.
-  std::vector<KernelRec> rec;
+  HostVec<KernelRec> rec;
   try {
-    rec.assign((size_t)p->M, KernelRec{});
+    rec.resize((size_t)p->M);
   } catch (...) {
     return GPAIR_ERR_INVALID_ARG;
   }
-  for (int64_t i = 0; i < p->M; ++i) {
-    rec[i].cx = h.kgeo[4 * i];
-    rec[i].cy = h.kgeo[4 * i + 1];
-    rec[i].cz = h.kgeo[4 * i + 2];
-  }
+  parallel_ranges(p->M, [&](int64_t b, int64_t e) {
+    for (int64_t i = b; i < e; ++i) {
+      KernelRec r{};
+      r.cx = h.kgeo[4 * i];
+      r.cy = h.kgeo[4 * i + 1];
+      r.cz = h.kgeo[4 * i + 2];
+      rec[i] = r;
+    }
+  });
   up(p->lay.krec, rec.data(), rec.size() * sizeof(KernelRec));
   up(p->lay.perm, h.perm.data(), h.perm.size() * sizeof(int32_t));
   up(p->lay.ftiles, h.ftiles.data(), h.ftiles.size() * sizeof(TileInfo));

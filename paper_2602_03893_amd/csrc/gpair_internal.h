@@ -4,12 +4,59 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
+#include <memory>
+#include <thread>
+#include <utility>
 #include <vector>
 
 #include "gpair.h"
 
 namespace gpair {
+
+// std::allocator that leaves trivially constructible elements uninitialised:
+// the planner's large host tables (GBs at 67 M kernels) are then first
+// written by parallel fill loops instead of a serial zero fill.
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = NoInitAlloc<U>;
+  };
+  NoInitAlloc() = default;
+  template <class U>
+  NoInitAlloc(const NoInitAlloc<U> &) {}
+  template <class U>
+  void construct(U *p) {
+    ::new ((void *)p) U;
+  }
+  template <class U, class... A>
+  void construct(U *p, A &&...a) {
+    ::new ((void *)p) U(std::forward<A>(a)...);
+  }
+};
+template <class T>
+using HostVec = std::vector<T, NoInitAlloc<T>>;
+
+// Host threads for the planner's O(M) passes.
+inline int host_threads() {
+  const unsigned n = std::thread::hardware_concurrency();
+  return (int)std::min<unsigned>(std::max<unsigned>(n, 1u), 16u);
+}
+
+// f(begin, end) over [0, n) in contiguous chunks, one per thread.
+template <class F>
+void parallel_ranges(int64_t n, F f) {
+  const int T = (int)std::min<int64_t>(host_threads(), std::max<int64_t>(1, n / 65536));
+  if (T <= 1) {
+    f((int64_t)0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int t = 0; t < T; ++t) th.emplace_back(f, n * t / T, n * (t + 1) / T);
+  for (auto &x : th) x.join();
+}
 
 // Bounding sphere and kernel range of one tile (a compact spatial block of
 // kernels, consecutive in the plan's permuted kernel order).
@@ -60,8 +107,8 @@ struct WorkspaceLayout {
 
 struct HostTables {
   std::vector<double> sens;      // [Nd][4]: x, y, z, |s|^2
-  std::vector<double> kgeo;      // [M][4] permuted centres
-  std::vector<int32_t> perm;     // [M] permuted index -> caller index
+  HostVec<double> kgeo;          // [M][4] permuted centres
+  HostVec<int32_t> perm;         // [M] permuted index -> caller index
   std::vector<TileInfo> ftiles;  // forward tiles
   std::vector<TileInfo> atiles;  // adjoint tiles
 };

@@ -15,6 +15,7 @@
 #include <cstring>
 #include <limits>
 #include <numeric>
+#include <thread>
 
 #include "gpair_internal.h"
 
@@ -38,6 +39,54 @@ inline uint64_t morton3(uint32_t ix, uint32_t iy, uint32_t iz) {
 
 bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
+// Sort of (key, index) records by key, then index: a parallel LSD radix sort
+// (11-bit digits, as many passes as the largest key needs).  The input is in
+// index order and every pass is stable, so equal keys keep index order.
+struct KeyIdx {
+  uint64_t key;
+  int32_t idx;
+};
+
+void parallel_sort(HostVec<KeyIdx> &v) {
+  const int64_t n = (int64_t)v.size();
+  uint64_t kmax = 0;
+  for (const KeyIdx &r : v) kmax = std::max(kmax, r.key);
+  int bits = 0;
+  while (bits < 64 && (kmax >> bits) != 0) ++bits;
+  constexpr int kDigit = 11, kBuckets = 1 << kDigit;
+  const int T = (int)std::min<int64_t>(host_threads(), std::max<int64_t>(1, n / 65536));
+  HostVec<KeyIdx> tmp((size_t)n);
+  std::vector<int64_t> count((size_t)T * kBuckets);
+  for (int shift = 0; shift < bits; shift += kDigit) {
+    std::fill(count.begin(), count.end(), 0);
+    std::vector<std::thread> th;
+    for (int t = 0; t < T; ++t)
+      th.emplace_back([&, t] {
+        int64_t *c = &count[(size_t)t * kBuckets];
+        for (int64_t i = n * t / T; i < n * (t + 1) / T; ++i)
+          ++c[(v[i].key >> shift) & (kBuckets - 1)];
+      });
+    for (auto &x : th) x.join();
+    th.clear();
+    // exclusive offsets in (digit, thread) order: stable
+    int64_t off = 0;
+    for (int d = 0; d < kBuckets; ++d)
+      for (int t = 0; t < T; ++t) {
+        const int64_t c = count[(size_t)t * kBuckets + d];
+        count[(size_t)t * kBuckets + d] = off;
+        off += c;
+      }
+    for (int t = 0; t < T; ++t)
+      th.emplace_back([&, t] {
+        int64_t *c = &count[(size_t)t * kBuckets];
+        for (int64_t i = n * t / T; i < n * (t + 1) / T; ++i)
+          tmp[c[(v[i].key >> shift) & (kBuckets - 1)]++] = v[i];
+      });
+    for (auto &x : th) x.join();
+    v.swap(tmp);
+  }
+}
+
 int level_for(int64_t tile) {  // smallest l with 8^l >= tile
   int l = 0;
   int64_t b = 1;
@@ -48,16 +97,29 @@ int level_for(int64_t tile) {  // smallest l with 8^l >= tile
   return l;
 }
 
-// Sorted unique values of one coordinate axis.
+// Sorted unique values of one coordinate axis: chunks sorted and made unique
+// in parallel, then the (short, for a lattice) lists merged.
 std::vector<float> axis_values(const float *x, int64_t m) {
-  std::vector<float> v(x, x + m);
+  const int T = (int)std::min<int64_t>(host_threads(), std::max<int64_t>(1, m / 65536));
+  std::vector<std::vector<float>> part(T);
+  std::vector<std::thread> th;
+  for (int t = 0; t < T; ++t)
+    th.emplace_back([&, t] {
+      std::vector<float> &v = part[t];
+      v.assign(x + m * t / T, x + m * (t + 1) / T);
+      std::sort(v.begin(), v.end());
+      v.erase(std::unique(v.begin(), v.end()), v.end());
+    });
+  for (auto &t : th) t.join();
+  std::vector<float> v;
+  for (const auto &p : part) v.insert(v.end(), p.begin(), p.end());
   std::sort(v.begin(), v.end());
   v.erase(std::unique(v.begin(), v.end()), v.end());
   return v;
 }
 
 struct Keys {
-  std::vector<uint64_t> key;
+  HostVec<uint64_t> key;
   bool lattice = false;
   double quantum = 0.0;  // point clouds: edge of one quantisation cell (m)
 };
@@ -72,16 +134,21 @@ Keys morton_keys(const gpair_geometry *g) {
   if (prod == (double)m && ux.size() < (1u << 21) && uy.size() < (1u << 21) &&
       uz.size() < (1u << 21)) {
     // Candidate full lattice: every kernel must map to a distinct lattice node.
-    std::vector<uint8_t> seen((size_t)m, 0);
+    HostVec<uint32_t> lin((size_t)m);
+    parallel_ranges(m, [&](int64_t b, int64_t e) {
+      for (int64_t k = b; k < e; ++k) {
+        uint32_t ix = (uint32_t)(std::lower_bound(ux.begin(), ux.end(), g->cx[k]) - ux.begin());
+        uint32_t iy = (uint32_t)(std::lower_bound(uy.begin(), uy.end(), g->cy[k]) - uy.begin());
+        uint32_t iz = (uint32_t)(std::lower_bound(uz.begin(), uz.end(), g->cz[k]) - uz.begin());
+        lin[k] = (uint32_t)(((size_t)iz * uy.size() + iy) * ux.size() + ix);
+        out.key[k] = morton3(ix, iy, iz);
+      }
+    });
+    std::vector<uint8_t> seen((size_t)m, 0);  // zeroed: read before written
     bool ok = true;
     for (int64_t k = 0; k < m && ok; ++k) {
-      uint32_t ix = (uint32_t)(std::lower_bound(ux.begin(), ux.end(), g->cx[k]) - ux.begin());
-      uint32_t iy = (uint32_t)(std::lower_bound(uy.begin(), uy.end(), g->cy[k]) - uy.begin());
-      uint32_t iz = (uint32_t)(std::lower_bound(uz.begin(), uz.end(), g->cz[k]) - uz.begin());
-      size_t lin = ((size_t)iz * uy.size() + iy) * ux.size() + ix;
-      if (seen[lin]) ok = false;
-      seen[lin] = 1;
-      out.key[k] = morton3(ix, iy, iz);
+      if (seen[lin[k]]) ok = false;
+      seen[lin[k]] = 1;
     }
     if (ok) {
       out.lattice = true;
@@ -95,22 +162,24 @@ Keys morton_keys(const gpair_geometry *g) {
   double q = ext > 0 ? ext / double((1u << 20) - 1) : 1.0;
   out.quantum = q;
   const float *c[3] = {g->cx, g->cy, g->cz};
-  for (int64_t k = 0; k < m; ++k) {
-    uint32_t ii[3];
-    for (int a = 0; a < 3; ++a) {
-      double t = std::floor(((double)c[a][k] - lo[a]) / q);
-      t = std::min(std::max(t, 0.0), double((1u << 20) - 1));
-      ii[a] = (uint32_t)t;
+  parallel_ranges(m, [&](int64_t b, int64_t e) {
+    for (int64_t k = b; k < e; ++k) {
+      uint32_t ii[3];
+      for (int a = 0; a < 3; ++a) {
+        double t = std::floor(((double)c[a][k] - lo[a]) / q);
+        t = std::min(std::max(t, 0.0), double((1u << 20) - 1));
+        ii[a] = (uint32_t)t;
+      }
+      out.key[k] = morton3(ii[0], ii[1], ii[2]);
     }
-    out.key[k] = morton3(ii[0], ii[1], ii[2]);
-  }
+  });
   return out;
 }
 
 // Cut the Morton-ordered kernels into tiles of at most `tile` members that
 // never cross an aligned Morton block of 8^level cells.
-std::vector<TileInfo> make_tiles(const std::vector<uint64_t> &sorted_keys,
-                                 const std::vector<double> &kgeo, int64_t tile,
+std::vector<TileInfo> make_tiles(const HostVec<uint64_t> &sorted_keys,
+                                 const HostVec<double> &kgeo, int64_t tile,
                                  int level) {
   std::vector<TileInfo> tiles;
   const int64_t m = (int64_t)sorted_keys.size();
@@ -219,24 +288,30 @@ gpair_status build_plan(const gpair_geometry *g, gpair_plan_s *p) {
 
   // Spatial order.
   Keys keys = morton_keys(g);
-  std::vector<int32_t> order((size_t)M);
-  std::iota(order.begin(), order.end(), 0);
-  std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-    return keys.key[a] < keys.key[b] || (keys.key[a] == keys.key[b] && a < b);
-  });
   HostTables &h = p->host;
-  h.perm = order;
-  h.kgeo.assign((size_t)M * 4, 0.0);
-  std::vector<uint64_t> skeys((size_t)M);
-  for (int64_t i = 0; i < M; ++i) {
-    int32_t k = order[i];
-    h.kgeo[4 * i + 0] = g->cx[k];
-    h.kgeo[4 * i + 1] = g->cy[k];
-    h.kgeo[4 * i + 2] = g->cz[k];
-    skeys[i] = keys.key[k];
+  HostVec<uint64_t> skeys((size_t)M);
+  {
+    HostVec<KeyIdx> rec((size_t)M);
+    parallel_ranges(M, [&](int64_t b, int64_t e) {
+      for (int64_t k = b; k < e; ++k) rec[k] = KeyIdx{keys.key[k], (int32_t)k};
+    });
+    keys.key.clear();
+    keys.key.shrink_to_fit();
+    parallel_sort(rec);
+    h.perm.resize((size_t)M);
+    h.kgeo.resize((size_t)M * 4);
+    parallel_ranges(M, [&](int64_t b, int64_t e) {
+      for (int64_t i = b; i < e; ++i) {
+        const int32_t k = rec[i].idx;
+        h.perm[i] = k;
+        h.kgeo[4 * i + 0] = g->cx[k];
+        h.kgeo[4 * i + 1] = g->cy[k];
+        h.kgeo[4 * i + 2] = g->cz[k];
+        h.kgeo[4 * i + 3] = 0.0;
+        skeys[i] = rec[i].key;
+      }
+    });
   }
-  keys.key.clear();
-  keys.key.shrink_to_fit();
   h.sens.assign((size_t)Nd * 4, 0.0);
   for (int32_t j = 0; j < Nd; ++j) {
     for (int a = 0; a < 3; ++a) h.sens[4 * j + a] = g->sensors[3 * j + a];
@@ -302,21 +377,40 @@ gpair_status build_plan(const gpair_geometry *g, gpair_plan_s *p) {
   // sensor.  Tile spheres give a lower bound; members are checked one by one
   // only where that bound is below the limit.
   const double near = 10.0 * g->sigma_max;
+  // Per tile and sensor: the lower bound of the distances; tiles closer than
+  // `near` are checked kernel by kernel.  Split over tiles across threads.
+  const int64_t nft = (int64_t)h.ftiles.size();
+  const int nth = host_threads();
+  std::vector<double> lbt(nth, std::numeric_limits<double>::infinity());
+  std::vector<uint8_t> nearf(nth, 0);
+  {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nth; ++t)
+      th.emplace_back([&, t] {
+        double lbm = std::numeric_limits<double>::infinity();
+        for (int64_t ti = nft * t / nth; ti < nft * (t + 1) / nth && !nearf[t]; ++ti) {
+          const TileInfo &T = h.ftiles[ti];
+          for (int32_t j = 0; j < Nd; ++j) {
+            double dx = h.sens[4 * j] - T.cx, dy = h.sens[4 * j + 1] - T.cy,
+                   dz = h.sens[4 * j + 2] - T.cz;
+            double lb = std::sqrt(dx * dx + dy * dy + dz * dz) - T.rho;
+            lbm = std::min(lbm, lb);
+            if (lb >= near) continue;
+            for (int32_t i = T.start; i < T.start + T.count; ++i) {
+              double ex = h.sens[4 * j] - h.kgeo[4 * i], ey = h.sens[4 * j + 1] - h.kgeo[4 * i + 1],
+                     ez = h.sens[4 * j + 2] - h.kgeo[4 * i + 2];
+              if (!(std::sqrt(ex * ex + ey * ey + ez * ez) >= near)) nearf[t] = 1;
+            }
+          }
+        }
+        lbt[t] = lbm;
+      });
+    for (auto &x : th) x.join();
+  }
   double lbmin = std::numeric_limits<double>::infinity();
-  for (size_t t = 0; t < h.ftiles.size(); ++t) {
-    const TileInfo &T = h.ftiles[t];
-    for (int32_t j = 0; j < Nd; ++j) {
-      double dx = h.sens[4 * j] - T.cx, dy = h.sens[4 * j + 1] - T.cy,
-             dz = h.sens[4 * j + 2] - T.cz;
-      double lb = std::sqrt(dx * dx + dy * dy + dz * dz) - T.rho;
-      lbmin = std::min(lbmin, lb);
-      if (lb >= near) continue;
-      for (int32_t i = T.start; i < T.start + T.count; ++i) {
-        double ex = h.sens[4 * j] - h.kgeo[4 * i], ey = h.sens[4 * j + 1] - h.kgeo[4 * i + 1],
-               ez = h.sens[4 * j + 2] - h.kgeo[4 * i + 2];
-        if (!(std::sqrt(ex * ex + ey * ey + ez * ez) >= near)) return GPAIR_ERR_NEAR_FIELD;
-      }
-    }
+  for (int t = 0; t < nth; ++t) {
+    if (nearf[t]) return GPAIR_ERR_NEAR_FIELD;
+    lbmin = std::min(lbmin, lbt[t]);
   }
   p->min_dist = std::max(lbmin, near);
 

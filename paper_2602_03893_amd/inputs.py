@@ -70,6 +70,18 @@ WORKLOADS = {
     "half": Workload("half", (128, 128, 64), 0.2e-3, 0.1e-3, 1024, 40e-3, 4096,
                      "vessels", 0, 0.01, 0),
 }
+# The simulation study's shapes (its results table): a 512 x 512 x 256 grid
+# (0.1 mm, so 51.2 x 51.2 x 25.6 mm) seen by a 102.4 mm square planar array
+# (20 mm below the grid centre, 7.2 mm below its lower face) or an R = 60 mm
+# hemisphere, each with 64, 256 or 1024 elements.
+for _n in (64, 256, 1024):
+    WORKLOADS[f"t1_planar_{_n}"] = Workload(
+        f"t1_planar_{_n}", (512, 512, 256), 0.1e-3, 0.05e-3, _n, 0.0, 4096, "vessels", 4,
+        0.0, 0, sigma_max=0.1e-3, extra={"array": "planar", "width": 102.4e-3,
+                                         "plane_z": -20e-3})
+    WORKLOADS[f"t1_hemi_{_n}"] = Workload(
+        f"t1_hemi_{_n}", (512, 512, 256), 0.1e-3, 0.05e-3, _n, 60e-3, 4096, "vessels", 4,
+        0.0, 0, sigma_max=0.1e-3)
 
 
 def grid_centres(nx, ny, nz, spacing):
@@ -77,8 +89,22 @@ def grid_centres(nx, ny, nz, spacing):
     xs = (np.arange(nx, dtype=np.float64) - (nx - 1) / 2.0) * spacing
     ys = (np.arange(ny, dtype=np.float64) - (ny - 1) / 2.0) * spacing
     zs = (np.arange(nz, dtype=np.float64) - (nz - 1) / 2.0) * spacing
-    Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
-    return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1).astype(np.float32)
+    out = np.empty((nz, ny, nx, 3), dtype=np.float32)
+    out[..., 0] = xs.astype(np.float32)[None, None, :]
+    out[..., 1] = ys.astype(np.float32)[None, :, None]
+    out[..., 2] = zs.astype(np.float32)[:, None, None]
+    return out.reshape(-1, 3)
+
+
+def planar_array(n, width, z):
+    """(n, 3) float32 points of a square array: sqrt(n) x sqrt(n) elements at
+    pitch width / sqrt(n), centred on the z axis, in the plane at height z."""
+    k = int(round(np.sqrt(n)))
+    if k * k != n:
+        raise ValueError("planar array: n must be a perfect square")
+    a = (np.arange(k, dtype=np.float64) - (k - 1) / 2.0) * (width / k)
+    Y, X = np.meshgrid(a, a, indexing="ij")
+    return np.stack([X.ravel(), Y.ravel(), np.full(n, z)], axis=1).astype(np.float32)
 
 
 def fibonacci_hemisphere(n, radius):
@@ -239,6 +265,13 @@ def uniform(shape, seed, lo=0.0, hi=1.0, dtype=np.float32):
     return np.random.default_rng(seed).uniform(lo, hi, shape).astype(dtype)
 
 
+def sensor_array(w: Workload):
+    """(N_d, 3) float32 sensor positions of a workload."""
+    if w.extra.get("array") == "planar":
+        return planar_array(w.n_sensors, w.extra["width"], w.extra["plane_z"])
+    return fibonacci_hemisphere(w.n_sensors, w.radius)
+
+
 def geometry_arrays(w: Workload):
     """(centres (M,3) float32, sensors (N_d,3) float32) of a workload."""
-    return grid_centres(*w.grid, w.spacing), fibonacci_hemisphere(w.n_sensors, w.radius)
+    return grid_centres(*w.grid, w.spacing), sensor_array(w)

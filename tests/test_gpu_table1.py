@@ -1,0 +1,89 @@
+"""GPU parity at the simulation study's largest shape: 512 x 512 x 256 =
+67,108,864 kernels (0.1 mm) with the planar (102.4 mm square) and
+hemispherical (R = 60 mm) arrays of its results table.  Checks that the plan,
+the tiling and the device memory hold at 8x the in vivo shape, for the direct
+operators (forward on sampled sensors, adjoint with the sigma-gradient on
+sampled kernels) and the ASSA operators, against the float64 oracles.
+
+Bar: relative L2 <= 1e-5, as at the smaller shapes.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import assa as S
+from oracle import ops as O
+from paper_2602_03893_amd import inputs as I
+from tests.conftest import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def case(name):
+    from paper_2602_03893_amd import Plan
+    w = I.WORKLOADS[name]
+    _say(f"case: {name}: {w.n_kernels} kernels, {w.n_sensors} sensors "
+         f"({w.extra.get('array', 'hemisphere')}), {w.n_samples} samples; building the plan")
+    cen, sen = I.geometry_arrays(w)
+    plan = Plan(cen, sen, w.n_samples, w.dt, w.c_sound, n_sigma=w.n_sigma, sigma_max=w.smax)
+    g = O.Geometry(cen, sen, w.n_samples, w.dt, w.t0, w.c_sound, w.n_sigma)
+    info = plan.info()
+    _say(f"  plan: {info['fwd_tiles']} tiles, workspace {info['workspace_bytes'] / 2**30:.2f} GiB, "
+         f"min distance {info['min_distance'] * 1e3:.2f} mm")
+    return w, plan, g
+
+
+def test_planar_256_direct_operators():
+    w, plan, g = case("t1_planar_256")
+    A = I.phantom(w)
+    sigma = I.uniform(w.n_kernels, seed=41, lo=0.5 * w.smax, hi=w.smax)
+    y = host(plan.forward(dev(A), dev(sigma)))
+    rows = np.random.default_rng(42).choice(w.n_sensors, 6, replace=False)
+    ref = O.forward(g.subset_sensors(rows), A, sigma.astype(np.float64))
+    err = rel_l2(y[rows], ref)
+    _say(f"  forward (6 sensors) rel L2 {err:.3e}")
+    assert np.abs(ref).max() > 0 and err <= TOL
+    delta = I.standard_normal((w.n_sensors, w.n_samples), seed=43)
+    gA, gS = plan.adjoint(dev(A), dev(sigma), dev(delta))
+    gA, gS = host(gA), host(gS)
+    ks = np.arange(7, w.n_kernels, 1024)
+    rA, rS = O.adjoint(g.subset_kernels(ks), A[ks], sigma[ks].astype(np.float64),
+                       delta.astype(np.float64))
+    eA, eS = rel_l2(gA[ks], rA), rel_l2(gS[ks], rS)
+    _say(f"  adjoint ({ks.size} kernels) gA {eA:.3e} gsigma {eS:.3e}")
+    assert eA <= TOL and eS <= TOL
+
+
+def test_hemisphere_64_assa_operators():
+    w, plan, g = case("t1_hemi_64")
+    grid = plan.assa_grid(w.sigma)
+    _say(f"  ASSA grid {grid}")
+    x = I.phantom(w)
+    y = host(plan.assa_forward(dev(x), w.sigma))
+    rows = np.random.default_rng(44).choice(w.n_sensors, 6, replace=False)
+    ref = S.forward(g.subset_sensors(rows), x.astype(np.float64), w.sigma)
+    err = rel_l2(y[rows], ref)
+    _say(f"  ASSA forward (6 sensors) rel L2 {err:.3e}")
+    assert np.abs(ref).max() > 0 and err <= TOL
+    delta = I.standard_normal((w.n_sensors, w.n_samples), seed=45)
+    got = host(plan.assa_adjoint(w.sigma, dev(delta)))
+    ks = np.arange(3, w.n_kernels, 512)
+    ref = S.adjoint(g.subset_kernels(ks), w.sigma, delta.astype(np.float64))
+    err = rel_l2(got[ks], ref)
+    _say(f"  ASSA back-projection ({ks.size} kernels) rel L2 {err:.3e}")
+    assert err <= TOL
