@@ -19,6 +19,8 @@ _LAZY = {
     "GpairError": ("_lib", "GpairError"),
     "GpairForward": ("autograd", "GpairForward"),
     "gpair_forward": ("autograd", "gpair_forward"),
+    "AssaForward": ("autograd", "AssaForward"),
+    "assa_forward": ("autograd", "assa_forward"),
 }
 
 

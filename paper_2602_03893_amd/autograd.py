@@ -33,3 +33,26 @@ class GpairForward(torch.autograd.Function):
 def gpair_forward(A, sigma, plan):
     """Differentiable y = A(x; sigma) for the given bound Plan."""
     return GpairForward.apply(A, sigma, plan)
+
+
+class AssaForward(torch.autograd.Function):
+    """y = S(h * P_up(x)) with one shared sigma (the ASSA operators); the
+    backward is the hand-written transpose (gpair_assa_adjoint).  sigma is a
+    Python float: the ASSA kernel h is not differentiated."""
+
+    @staticmethod
+    def forward(ctx, x, sigma, plan):
+        ctx.plan = plan
+        ctx.sigma = float(sigma)
+        return plan.assa_forward(x.contiguous(), ctx.sigma)
+
+    @staticmethod
+    def backward(ctx, grad_y):
+        if not ctx.needs_input_grad[0]:
+            return None, None, None
+        return ctx.plan.assa_adjoint(ctx.sigma, grad_y.contiguous()), None, None
+
+
+def assa_forward(x, sigma, plan):
+    """Differentiable ASSA forward y = S(h * P_up(x)) for a bound Plan."""
+    return AssaForward.apply(x, sigma, plan)

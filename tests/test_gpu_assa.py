@@ -160,6 +160,32 @@ def test_single_kernel_and_zero_amplitudes():
     assert not np.any(host(plan.assa_forward(dev(np.zeros(1, np.float32)), 0.07e-3)))
 
 
+def test_autograd_function(toy):
+    """The autograd Function: its gradient equals the oracle's back-projection
+    of dL/dy, and a torch loss on it descends under a torch optimiser."""
+    from paper_2602_03893_amd import assa_forward
+    w, plan, g = toy
+    x = torch.tensor(I.uniform(w.n_kernels, seed=31), device="cuda", requires_grad=True)
+    target = dev(S.forward(g, I.phantom(w).astype(np.float64), w.sigma))
+    y = assa_forward(x, w.sigma, plan)
+    loss = 0.5 * torch.sum((y - target) ** 2)
+    loss.backward()
+    resid = (y - target).detach()
+    ref = S.adjoint(g, w.sigma, host(resid))
+    err = rel_l2(host(x.grad), ref)
+    _say(f"  autograd gradient rel L2 {err:.3e}")
+    assert err <= TOL
+    opt = torch.optim.Adam([x], lr=1e-2)
+    losses = []
+    for _ in range(10):
+        opt.zero_grad()
+        loss = 0.5 * torch.sum((assa_forward(x, w.sigma, plan) - target) ** 2)
+        loss.backward()
+        opt.step()
+        losses.append(float(loss))
+    assert losses[-1] < losses[0]
+
+
 def test_invalid_arguments(toy):
     from paper_2602_03893_amd import GpairError
     w, plan, g = toy
