@@ -33,13 +33,13 @@ FLOP_PAIR = 25        # distance (3 sub, 3 fma, sqrt), window bounds, 1/(2r), ta
 # by the sha256 prefix of the kernel source they were measured on; when the source
 # differs, the figure no longer applies and `traffic` is null.
 MEASURED_TRAFFIC = {
-    "876d3f5981144dcd": {"forward_kernel": 5.396e9, "adjoint_kernel": 0.696e9},
+    "1a6a519aca5f58c5": {"forward_kernel": 2.292e9, "adjoint_kernel": 0.696e9},
 }
 
 
 # The same for the ASSA kernels (assa.hip).
 MEASURED_TRAFFIC_ASSA = {
-    "fb549a835c469678": {"assa_forward_kernel": 5.977e9, "assa_adjoint_kernel": 0.851e9},
+    "eeda02f9d007075a": {"assa_forward_kernel": 2.839e9, "assa_adjoint_kernel": 0.852e9},
 }
 
 

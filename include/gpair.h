@@ -88,8 +88,9 @@ int gpair_abi_version(void);
  *               power of two in [64, 8192].
  *  adj_tile     most kernels per adjoint workgroup, 0 = automatic (256),
  *               else 64, 128 or 256.
- *  fwd_waves    sensor groups of 64 per forward workgroup, 0 = automatic,
- *               else 1, 2 or 4 (reduced if the LDS segments do not fit).
+ *  fwd_waves    waves per forward workgroup (they split a tile's kernels and
+ *               share one trace segment), 0 = automatic (4), else 1, 2, 4
+ *               or 8.
  */
 typedef struct gpair_geometry {
   int64_t n_kernels;
@@ -118,7 +119,7 @@ typedef struct gpair_plan_info {
   int32_t n_samples;
   int32_t fwd_tile;          /* kernels per forward workgroup              */
   int32_t adj_tile;          /* kernels per adjoint workgroup              */
-  int32_t fwd_waves;         /* sensor groups per forward workgroup        */
+  int32_t fwd_waves;         /* waves per forward workgroup                */
   int64_t fwd_tiles;         /* number of forward tiles                    */
   int64_t adj_tiles;         /* number of adjoint tiles                    */
   int32_t fwd_segment;       /* samples in a forward LDS trace segment     */
@@ -172,7 +173,10 @@ gpair_status gpair_plan_get_info(gpair_plan p, gpair_plan_info *info);
  * i.e. Eq. (single_forward) summed over the kernels by linearity of the wave
  * equation, with the window of the "3 sigma principle" (inclusive) and
  * samples outside [0, n_samples) dropped.  r_jk = |s_j - c_k| and the window
- * membership are decided in float64; taps are evaluated in float32.
+ * membership are decided in float64; taps are evaluated in float32.  The
+ * partial sum of each group of nearby kernels (a tile) at a sensor is carried
+ * in 32-bit fixed point whose unit is 2^-30 of a bound on that sum
+ * (sum_k |A_k| sigma_max e^{-1/2} / (2 r_min)), then added to y in float32.
  *  A      device float32 [n_kernels]  amplitudes A_k (any sign).
  *  sigma  device float32 [n_kernels]  widths sigma_k in (0, sigma_max].
  *  y      device float32 [n_sensors][n_samples], overwritten.

@@ -15,12 +15,17 @@
 //  * Tap stage, float32: d_i = d_0 - i Delta, and the Gaussian factor by the
 //    exact recurrence e_{i+1} = e_i q_i, q_{i+1} = q_i rq (two exp2 per pair
 //    instead of one per tap).
-//  * Forward: one wave = one tile of kernels x 64 sensors; lane = sensor, the
-//    kernel loop is wave-uniform (kernel data in scalar registers).  Each lane
-//    owns one LDS column: the trace segment of its sensor over the tile's time
-//    shell, so taps accumulate by plain read-modify-write without bank
-//    conflicts.  At the end the segments are added to y with one coalesced
-//    float atomic per sample (tile-sensor partial sums), not one per tap.
+//  * Forward: one workgroup = one tile of kernels x 64 sensors; lane = sensor,
+//    the kernel loop is wave-uniform (kernel data in scalar registers) and the
+//    workgroup's waves split the tile's kernels.  The waves share one LDS
+//    trace segment per sensor over the tile's time shell, into which taps go
+//    as 32-bit fixed-point integer adds (ds_add_u32 issues without waiting,
+//    where a float add or a read-modify-write waits for LDS every tap).  The
+//    fixed-point unit is per sensor: 2^-30 of a bound on any sum the tile can
+//    put into one sample (sum_k |A_k| * sigma_max e^{-1/2} / (2 r_low)), so no
+//    sum can overflow and each tap is rounded to 2^-31 of that bound.  At the
+//    end the segment goes back to float32 and is added to y with one
+//    coalesced float atomic per sample (tile-sensor partial sums).
 //  * Adjoint: one workgroup = one tile of kernels; lane = kernel, the sensor
 //    loop is uniform.  For each stage of 64 sensors the residual over the
 //    tile's time shell is staged in LDS; every lane gathers its taps from it.
@@ -108,42 +113,6 @@ __device__ __forceinline__ PairTerms pair_terms(double sx, double sy, double sz,
 // ---------------------------------------------------------------------------
 // Forward.
 // ---------------------------------------------------------------------------
-struct FwdArgs {
-  const double4 *sens;
-  const TileInfo *tiles;
-  float *y;
-  int64_t nlogical;
-  int32_t Nd, Nt, nsg, nsgw, L;
-  double inv_vdt, t0_over_dt, hmax, vdt;
-};
-
-// Add the taps of one kernel-sensor pair into the lane's segment column p
-// (stride 64 floats): NT samples, of which the first nvalid are inside the
-// window (nvalid = ntap - 1 or ntap, and ntap >= NT - 2, so only the last
-// three can be outside).  All reads are issued before the arithmetic so their
-// latency overlaps it; consecutive reads and writes pair up (one paired LDS
-// access per two samples).
-template <int NT>
-__device__ __forceinline__ void taps_rmw(float *p, float f, float q, float d, float rq,
-                                         float vdt, int nvalid) {
-  float old[NT];
-#pragma unroll
-  for (int i = 0; i < NT; ++i) old[i] = p[i * kWave];
-  float t[NT];
-#pragma unroll
-  for (int i = 0; i < NT; ++i) {
-    t[i] = f * d;
-    d -= vdt;
-    f *= q;
-    q *= rq;
-  }
-#pragma unroll
-  for (int i = (NT - 3 > 0 ? NT - 3 : 0); i < NT; ++i)
-    if (i >= nvalid) t[i] = 0.0f;
-#pragma unroll
-  for (int i = 0; i < NT; ++i) p[i * kWave] = old[i] + t[i];
-}
-
 // Everything the tap loop of one kernel-sensor pair needs.
 struct Taps {
   float f;       // w * exp(-d0^2 / (2 sigma^2)) with w = A / (2 r)
@@ -168,18 +137,59 @@ __device__ __forceinline__ Taps pair_taps(const double4 &s, const KernelRec &r, 
   return t;
 }
 
-// Taps of one pair with any tap count (the general path).
-__device__ __forceinline__ void add_taps_any(float *p, const Taps &t, const KernelRec &r,
-                                             float vdt_f) {
-  float f = t.f, q = t.q, d = t.d;
-  const int nfull = r.ntap - 1;
-  for (int i = 0; i < nfull; ++i) {
-    p[i * kWave] += f * d;
-    d -= vdt_f;
+// Add v (in fixed-point units) to an LDS word, rounded half up with one
+// instruction (floor(v + 1/2) then convert; the compiler emits three).
+__device__ __forceinline__ void lds_add(int *p, float v) {
+  int n;
+  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(n) : "v"(v));
+  __hip_atomic_fetch_add(p, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Add the taps of one kernel-sensor pair into the lane's segment column p
+// (stride 64 words), f already in fixed-point units: NT samples, of which the
+// first nvalid are inside the window (nvalid = ntap - 1 or ntap, and ntap >=
+// NT - 2, so only the last three can be outside).
+template <int NT>
+__device__ __forceinline__ void taps_add(int *p, float f, float q, float d, float rq,
+                                         float vdt, int nvalid) {
+  float t[NT];
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    t[i] = f * d;
+    d -= vdt;
     f *= q;
-    q *= r.rq;
+    q *= rq;
   }
-  p[nfull * kWave] += t.last_ok ? f * d : 0.0f;
+#pragma unroll
+  for (int i = (NT - 3 > 0 ? NT - 3 : 0); i < NT; ++i)
+    if (i >= nvalid) t[i] = 0.0f;
+#pragma unroll
+  for (int i = 0; i < NT; ++i) lds_add(p + i * kWave, t[i]);
+}
+
+// Taps of one pair whose tap count n is wave-uniform but not known at compile
+// time: a scalar branch to the unrolled form, a loop beyond 18 taps.
+__device__ __forceinline__ void taps_add_n(int n, int *p, float f, float q, float d, float rq,
+                                           float vdt, bool last_ok) {
+  const int nvalid = n - (last_ok ? 0 : 1);
+  switch (n) {
+#define GPAIR_TAPS_CASE(k) \
+  case k: taps_add<k>(p, f, q, d, rq, vdt, nvalid); return;
+    GPAIR_TAPS_CASE(1) GPAIR_TAPS_CASE(2) GPAIR_TAPS_CASE(3) GPAIR_TAPS_CASE(4)
+    GPAIR_TAPS_CASE(5) GPAIR_TAPS_CASE(6) GPAIR_TAPS_CASE(7) GPAIR_TAPS_CASE(8)
+    GPAIR_TAPS_CASE(9) GPAIR_TAPS_CASE(10) GPAIR_TAPS_CASE(11) GPAIR_TAPS_CASE(12)
+    GPAIR_TAPS_CASE(13) GPAIR_TAPS_CASE(14) GPAIR_TAPS_CASE(15) GPAIR_TAPS_CASE(16)
+    GPAIR_TAPS_CASE(17) GPAIR_TAPS_CASE(18)
+#undef GPAIR_TAPS_CASE
+    default: break;
+  }
+  for (int i = 0; i < n - 1; ++i) {
+    lds_add(p + i * kWave, f * d);
+    d -= vdt;
+    f *= q;
+    q *= rq;
+  }
+  lds_add(p + (n - 1) * kWave, last_ok ? f * d : 0.0f);
 }
 
 struct FwdLoop {
@@ -187,15 +197,17 @@ struct FwdLoop {
   double4 s;
   int nb, L, omax;
   double inv_vdt, t0_over_dt, vdt;
-  float vdt_f;
+  float vdt_f, iu;
 };
 
-// The kernel loop of one wave over its tile when every kernel of the tile
-// has NT - 2 .. NT taps.  Kernels go in pairs: both pair stages sit in one
-// straight-line block, so their float64 chains interleave, and the records of
-// the next pair are fetched meanwhile (clamped to the tile's last record).
+// The kernel loop of one wave over records [k0, kend) of its tile when every
+// kernel of the tile has NT - 2 .. NT taps.  Kernels go in pairs: both pair
+// stages sit in one straight-line block, so their float64 chains interleave,
+// and the records of the next pair are fetched meanwhile (clamped to the last
+// record).  (Four per iteration need 130 VGPRs and run slower.)
 template <int NT>
-__device__ __forceinline__ void kernel_loop(const FwdLoop &c, float *col, int k0, int kend) {
+__device__ __forceinline__ void kernel_loop(const FwdLoop &c, int *col, int k0, int kend) {
+  if (k0 >= kend) return;
   const int last = kend - 1;
   const int pend = k0 + ((kend - k0) & ~1);
   KernelRec ra = c.krec[k0], rb = c.krec[min(k0 + 1, last)];
@@ -206,60 +218,104 @@ __device__ __forceinline__ void kernel_loop(const FwdLoop &c, float *col, int k0
     const int nva = ra.ntap - (ta.last_ok ? 0 : 1), nvb = rb.ntap - (tb.last_ok ? 0 : 1);
     ra = c.krec[min(k + 2, last)];
     rb = c.krec[min(k + 3, last)];
-    taps_rmw<NT>(col + ta.o * kWave, ta.f, ta.q, ta.d, rqa, c.vdt_f, nva);
-    taps_rmw<NT>(col + tb.o * kWave, tb.f, tb.q, tb.d, rqb, c.vdt_f, nvb);
+    taps_add<NT>(col + ta.o * kWave, ta.f * c.iu, ta.q, ta.d, rqa, c.vdt_f, nva);
+    taps_add<NT>(col + tb.o * kWave, tb.f * c.iu, tb.q, tb.d, rqb, c.vdt_f, nvb);
   }
   if (pend < kend) {
     const Taps t = pair_taps(c.s, ra, c.nb, c.omax, c.inv_vdt, c.t0_over_dt, c.vdt);
-    taps_rmw<NT>(col + t.o * kWave, t.f, t.q, t.d, ra.rq, c.vdt_f,
+    taps_add<NT>(col + t.o * kWave, t.f * c.iu, t.q, t.d, ra.rq, c.vdt_f,
                  ra.ntap - (t.last_ok ? 0 : 1));
   }
 }
 
+// The same loop for a tile whose kernels differ in width by more than two
+// taps: each pair branches on its own tap count.
+__device__ __forceinline__ void kernel_loop_mixed(const FwdLoop &c, int *col, int k0, int kend) {
+  if (k0 >= kend) return;
+  const int last = kend - 1;
+  const int pend = k0 + ((kend - k0) & ~1);
+  KernelRec ra = c.krec[k0], rb = c.krec[min(k0 + 1, last)];
+  for (int k = k0; k < pend; k += 2) {
+    const Taps ta = pair_taps(c.s, ra, c.nb, c.L - 1 - ra.ntap, c.inv_vdt, c.t0_over_dt, c.vdt);
+    const Taps tb = pair_taps(c.s, rb, c.nb, c.L - 1 - rb.ntap, c.inv_vdt, c.t0_over_dt, c.vdt);
+    const float rqa = ra.rq, rqb = rb.rq;
+    const int na = ra.ntap, nb = rb.ntap;
+    ra = c.krec[min(k + 2, last)];
+    rb = c.krec[min(k + 3, last)];
+    taps_add_n(na, col + ta.o * kWave, ta.f * c.iu, ta.q, ta.d, rqa, c.vdt_f, ta.last_ok);
+    taps_add_n(nb, col + tb.o * kWave, tb.f * c.iu, tb.q, tb.d, rqb, c.vdt_f, tb.last_ok);
+  }
+  if (pend < kend) {
+    const Taps t = pair_taps(c.s, ra, c.nb, c.L - 1 - ra.ntap, c.inv_vdt, c.t0_over_dt, c.vdt);
+    taps_add_n(ra.ntap, col + t.o * kWave, t.f * c.iu, t.q, t.d, ra.rq, c.vdt_f, t.last_ok);
+  }
+}
+
+struct FwdArgs {
+  const double4 *sens;
+  const TileInfo *tiles;
+  float *y;
+  int64_t nlogical;
+  int32_t Nd, Nt, nsg, L;
+  double inv_vdt, t0_over_dt, hmax, vdt;
+  double peak;      // bound of |A/(2r) d e^{-d^2/2 sigma^2}| r / |A| over sigma <= sigma_max
+  double min_dist;  // lower bound of every kernel-sensor distance (m)
+};
+
 // The record array is a direct kernel argument (const, restrict) so that its
-// uniform loads stay scalar loads next to the LDS stores of the tap loop.
+// uniform loads stay scalar loads next to the LDS adds of the tap loop.
 template <int WAVES>
 __global__ __launch_bounds__(WAVES * kWave) void forward_kernel(
     const KernelRec *__restrict__ krec, FwdArgs a) {
-  extern __shared__ float seg_all[];  // [WAVES][L][64]
-
+  extern __shared__ int seg[];  // [L][64]: sample-major, one column per sensor
   const int64_t logical = xcd_logical_block(a.nlogical);
   if (logical >= a.nlogical) return;
-  const int64_t tile = logical / a.nsgw;
-  const int sgw = (int)(logical - tile * a.nsgw);
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int sg = sgw * WAVES + wave;
-  const bool wave_live = sg < a.nsg;
-  float *const seg = seg_all + (size_t)wave * a.L * kWave;
-  float *const col = seg + lane;
-
+  const int64_t tile = logical / a.nsg;
+  const int sg = (int)(logical - tile * a.nsg);
+  const int t = threadIdx.x;
+  const int lane = t & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int j = sg * kWave + lane;
   const double4 s = a.sens[j < a.Nd ? j : a.Nd - 1];
   const TileInfo T = a.tiles[tile];
-  int nb;
+  double R;
   {
     const double dx = s.x - T.cx, dy = s.y - T.cy, dz = s.z - T.cz;
-    const double R = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
-    nb = (int)floor((R - T.rho) * a.inv_vdt - a.t0_over_dt - a.hmax) - 1;
+    R = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
   }
+  const int nb = (int)floor((R - T.rho) * a.inv_vdt - a.t0_over_dt - a.hmax) - 1;
+  for (int i = t; i < a.L * kWave; i += WAVES * kWave) seg[i] = 0;
 
-  if (!wave_live) return;  // the last workgroup may have fewer sensor groups
-  for (int i = 0; i < a.L; ++i) col[i * kWave] = 0.0f;
-
-  // Tap-count range of the tile (kernels' ntap), read once per wave.
+  // Tap-count range and sum of |A_k| of the tile, read once per wave.  Every
+  // wave adds the same values in the same order (the butterfly gives every
+  // lane the same sum, as float addition commutes), so all waves of the
+  // workgroup derive the same fixed-point unit.
   int nmin = 1 << 30, nmax = 0;
+  float asum = 0.0f;
   for (int i = T.start + lane; i < T.start + T.count; i += kWave) {
     const int n = krec[i].ntap;
     nmin = min(nmin, n);
     nmax = max(nmax, n);
+    asum += fabsf(krec[i].amp);
   }
   for (int off = 32; off > 0; off >>= 1) {
     nmin = min(nmin, __shfl_xor(nmin, off, kWave));
     nmax = max(nmax, __shfl_xor(nmax, off, kWave));
+    asum += __shfl_xor(asum, off, kWave);
   }
   nmin = __builtin_amdgcn_readfirstlane(nmin);
   nmax = __builtin_amdgcn_readfirstlane(nmax);
+  // Every member is at distance >= r_low, so every sample's sum over the tile
+  // is at most `bound` = 2^30 units: with each tap rounded to half a unit the
+  // integer stays below 2^31 for any tile size used here.  A non-finite asum
+  // gives unit = inf or NaN and a non-finite output.
+  const double r_low = fmax(R - T.rho, a.min_dist);
+  const double bound = (double)asum * a.peak / r_low;
+  const float unit = (float)(bound * 0x1p-30);
+  const float iu = bound > 0.0 ? (float)(0x1p30 / bound) : 0.0f;
+  __syncthreads();  // the segment is zero
+
+  int *const col = seg + lane;
   FwdLoop c;
   c.krec = krec;
   c.s = s;
@@ -269,65 +325,47 @@ __global__ __launch_bounds__(WAVES * kWave) void forward_kernel(
   c.t0_over_dt = a.t0_over_dt;
   c.vdt = a.vdt;
   c.vdt_f = (float)a.vdt;
-  const int kend = T.start + T.count;
+  c.iu = iu;
+  const int per = (T.count + WAVES - 1) / WAVES;
+  const int k0 = T.start + wave * per;
+  const int k1 = min(T.start + T.count, k0 + per);
   if (nmin >= nmax - 2 && nmax >= 2 && nmax <= 18) {
     c.omax = a.L - 1 - nmax;
     switch (nmax) {
 #define GPAIR_FWD_CASE(n) \
-  case n: kernel_loop<n>(c, col, T.start, kend); break;
+  case n: kernel_loop<n>(c, col, k0, k1); break;
       GPAIR_FWD_CASE(2) GPAIR_FWD_CASE(3) GPAIR_FWD_CASE(4) GPAIR_FWD_CASE(5)
       GPAIR_FWD_CASE(6) GPAIR_FWD_CASE(7) GPAIR_FWD_CASE(8) GPAIR_FWD_CASE(9)
       GPAIR_FWD_CASE(10) GPAIR_FWD_CASE(11) GPAIR_FWD_CASE(12) GPAIR_FWD_CASE(13)
       GPAIR_FWD_CASE(14) GPAIR_FWD_CASE(15) GPAIR_FWD_CASE(16) GPAIR_FWD_CASE(17)
-      default: kernel_loop<18>(c, col, T.start, kend); break;
+      default: kernel_loop<18>(c, col, k0, k1); break;
 #undef GPAIR_FWD_CASE
     }
   } else {
-    // Widely varying widths inside one tile: per-kernel tap loop.
-    for (int k = T.start; k < kend; ++k) {
-      const KernelRec r = krec[k];
-      const Taps t = pair_taps(s, r, nb, a.L - 1 - r.ntap, a.inv_vdt, a.t0_over_dt, a.vdt);
-      add_taps_any(col + t.o * kWave, t, r, c.vdt_f);
-    }
+    kernel_loop_mixed(c, col, k0, k1);
   }
-  // The segment is private to this wave and a wave's LDS operations complete
-  // in issue order, so the flush below (which reads other lanes' columns)
-  // needs no workgroup barrier; this only keeps the compiler from moving
-  // memory operations across.
-  __builtin_amdgcn_wave_barrier();
+  __syncthreads();
 
-  // Flush the wave's 64 rows: lanes walk the samples of one row so that
-  // consecutive lanes add to consecutive addresses of y (coalesced float
-  // atomics; per-lane rows would scatter one atomic per cache line, which
-  // measured twice as slow with dense amplitudes).
-  if (a.L <= kWave) {
-    // One sample per lane: rows in groups of 8, all reads before the adds.
-    const bool in_seg = lane < a.L;
-    for (int row0 = 0; row0 < kWave; row0 += 8) {
-      float v[8];
-      int n[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        v[u] = in_seg ? seg[lane * kWave + row0 + u] : 0.0f;
-        n[u] = __builtin_amdgcn_readlane(nb, row0 + u) + lane;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int jr = sg * kWave + row0 + u;
-        if (jr < a.Nd && n[u] >= 0 && n[u] < a.Nt && v[u] != 0.0f)
-          unsafeAtomicAdd(a.y + (int64_t)jr * a.Nt + n[u], v[u]);
-      }
-    }
-    return;
+  // Back to float32 (each lane's own unit), row c stored rotated by c columns
+  // so that the flush below reads a row of the transpose without bank
+  // conflicts.  Each row is read and rewritten by one wave.
+  for (int cr = wave; cr < a.L; cr += WAVES) {
+    const int v = col[cr * kWave];
+    seg[cr * kWave + ((lane + cr) & (kWave - 1))] = __float_as_int((float)v * unit);
   }
-  for (int row = 0; row < kWave; ++row) {
+  __syncthreads();
+
+  // Flush: one sensor row per wave at a time, lanes walk its samples so that
+  // consecutive lanes add to consecutive addresses of y (coalesced float
+  // atomics; per-lane rows would scatter one atomic per cache line).
+  for (int row = wave; row < kWave; row += WAVES) {
     const int jr = sg * kWave + row;
     if (jr >= a.Nd) break;
     const int nbr = __builtin_amdgcn_readlane(nb, row);
     float *yrow = a.y + (int64_t)jr * a.Nt;
-    for (int sidx = lane; sidx < a.L; sidx += kWave) {
-      const int n = nbr + sidx;
-      const float v = seg[sidx * kWave + row];
+    for (int cs = lane; cs < a.L; cs += kWave) {
+      const int n = nbr + cs;
+      const float v = __int_as_float(seg[cs * kWave + ((row + cs) & (kWave - 1))]);
       if (n >= 0 && n < a.Nt && v != 0.0f) unsafeAtomicAdd(yrow + n, v);
     }
   }
@@ -528,20 +566,24 @@ hipError_t launch_forward(const gpair_plan_s *p, float *y, hipStream_t s) {
   a.Nd = p->Nd;
   a.Nt = p->Nt;
   a.nsg = (p->Nd + kWave - 1) / kWave;
-  const int W = p->fwd_waves;
-  a.nsgw = (a.nsg + W - 1) / W;
-  a.nlogical = (int64_t)p->host.ftiles.size() * a.nsgw;
+  a.nlogical = (int64_t)p->host.ftiles.size() * a.nsg;
   a.L = p->Lf;
   a.inv_vdt = p->inv_vdt;
   a.t0_over_dt = p->t0_over_dt;
   a.hmax = p->hmax;
   a.vdt = p->vdt;
-  const size_t lds = (size_t)W * p->Lf * kWave * sizeof(float);
+  // max over d of |d| e^{-d^2/(2 sigma^2)} is sigma e^{-1/2}; the record
+  // builder clamps sigma to sigma_max (1 + 1e-6), and the last factor covers
+  // the float32 rounding of the taps.
+  a.peak = 0.5 * p->sigma_max * (1.0 + 1e-6) * 0.60653065971263342 * (1.0 + 1e-5);
+  a.min_dist = p->min_dist;
+  const size_t lds = (size_t)p->Lf * kWave * sizeof(int);
   const unsigned int grid = xcd_grid(a.nlogical);
-  switch (W) {
+  switch (p->fwd_waves) {
     case 1: forward_kernel<1><<<grid, kWave, lds, s>>>(ws_krec(p), a); break;
     case 2: forward_kernel<2><<<grid, 2 * kWave, lds, s>>>(ws_krec(p), a); break;
-    default: forward_kernel<4><<<grid, 4 * kWave, lds, s>>>(ws_krec(p), a); break;
+    case 4: forward_kernel<4><<<grid, 4 * kWave, lds, s>>>(ws_krec(p), a); break;
+    default: forward_kernel<8><<<grid, 8 * kWave, lds, s>>>(ws_krec(p), a); break;
   }
   return hipGetLastError();
 }

@@ -261,7 +261,8 @@ gpair_status build_plan(const gpair_geometry *g, gpair_plan_s *p) {
     return GPAIR_ERR_INVALID_ARG;
   if (g->adj_tile != 0 && g->adj_tile != 64 && g->adj_tile != 128 && g->adj_tile != 256)
     return GPAIR_ERR_INVALID_ARG;
-  if (g->fwd_waves != 0 && g->fwd_waves != 1 && g->fwd_waves != 2 && g->fwd_waves != 4)
+  if (g->fwd_waves != 0 && g->fwd_waves != 1 && g->fwd_waves != 2 && g->fwd_waves != 4 &&
+      g->fwd_waves != 8)
     return GPAIR_ERR_INVALID_ARG;
   const int64_t M = g->n_kernels;
   const int32_t Nd = g->n_sensors;
@@ -338,15 +339,17 @@ gpair_status build_plan(const gpair_geometry *g, gpair_plan_s *p) {
     return std::min(std::max(l, 0), 20);
   };
 
-  // Forward: a wave holds one LDS trace segment of Lf samples for 64 sensors,
-  // so the tile size sets both the work per wave and the LDS per wave.  Tiles
-  // of 8 x 8 x 4 lattice nodes keep a segment near 12 KiB (measured best at
-  // the paper-scale shape); smaller tiles are used only when the problem is
-  // too small to give every CU several waves.
+  // Forward: a workgroup holds one LDS trace segment of Lf samples for 64
+  // sensors, and its waves split the tile's kernels, so the tile size sets
+  // both the work per workgroup and its LDS.  Tiles of 1024 lattice nodes
+  // (a segment near 18 KiB) measured best at the paper-scale shape, for the
+  // direct forward and the ASSA forward, which uses the same tiles; smaller
+  // tiles are used only when the problem is too small to give every CU
+  // several workgroups.
   const int64_t nsg = (Nd + kWave - 1) / kWave;
   int64_t Tf = g->fwd_tile;
   if (Tf == 0) {
-    Tf = 256;
+    Tf = 1024;
     while (Tf > 64 && ((M + Tf - 1) / Tf) * nsg < 4096) Tf /= 2;
   }
   const int64_t Lcap = kMaxSegmentBytes / (kWave * 4);
@@ -358,9 +361,7 @@ gpair_status build_plan(const gpair_geometry *g, gpair_plan_s *p) {
   }
   if (p->Lf > Lcap) return GPAIR_ERR_INVALID_ARG;
   p->fwd_tile = (int32_t)Tf;
-  int W = g->fwd_waves ? g->fwd_waves : 4;
-  while (W > 1 && ((int64_t)W * p->Lf * kWave * 4 > kMaxSegmentBytes || W > nsg)) W /= 2;
-  p->fwd_waves = W;
+  p->fwd_waves = g->fwd_waves ? g->fwd_waves : 4;
 
   int64_t Ta = g->adj_tile ? g->adj_tile : 256;
   for (;;) {

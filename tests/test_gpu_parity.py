@@ -21,10 +21,10 @@ def _say(msg):
 
 
 def make_case(centres, sensors, n_samples, sigma_max, dt=I.DT, t0=0.0, c=I.C_SOUND,
-              nsig=3.0, fwd_tile=0, adj_tile=0):
+              nsig=3.0, fwd_tile=0, adj_tile=0, fwd_waves=0):
     from paper_2602_03893_amd import Plan
     plan = Plan(centres, sensors, n_samples, dt, c, n_sigma=nsig, sigma_max=sigma_max,
-                t0=t0, fwd_tile=fwd_tile, adj_tile=adj_tile)
+                t0=t0, fwd_tile=fwd_tile, adj_tile=adj_tile, fwd_waves=fwd_waves)
     g = O.Geometry(centres, sensors, n_samples, dt, t0, c, nsig)
     return plan, g
 
@@ -109,12 +109,14 @@ def test_adjointness_on_gpu(toy):
     assert abs(lhs - rhs) <= 1e-6 * abs(lhs)
 
 
-@pytest.mark.parametrize("fwd_tile,adj_tile", [(64, 64), (256, 128), (1024, 256)])
-def test_ragged_point_cloud_clipped_windows(fwd_tile, adj_tile):
+@pytest.mark.parametrize("fwd_tile,adj_tile,fwd_waves",
+                         [(64, 64, 1), (256, 128, 2), (1024, 256, 4), (64, 256, 4)])
+def test_ragged_point_cloud_clipped_windows(fwd_tile, adj_tile, fwd_waves):
     """A random point cloud (not a lattice), N_d not a multiple of 64, tiles of
-    several sizes, and a time origin that cuts the earliest pulses at sample 0
+    several sizes (the last one partly filled), 1, 2 or 4 waves splitting each
+    forward tile, and a time origin that cuts the earliest pulses at sample 0
     and the latest at sample N_t - 1."""
-    _say(f"case: point cloud M=1000, N_d=70, tiles {fwd_tile}/{adj_tile}")
+    _say(f"case: point cloud M=1000, N_d=70, tiles {fwd_tile}/{adj_tile}, {fwd_waves} waves")
     rng = np.random.default_rng(8)
     cen = rng.uniform(-1.5e-3, 1.5e-3, (1000, 3)).astype(np.float32)
     sen = I.fibonacci_hemisphere(70, 12e-3)
@@ -123,13 +125,38 @@ def test_ragged_point_cloud_clipped_windows(fwd_tile, adj_tile):
     t0 = 11e-3 / I.C_SOUND
     nt = int((2e-3 / I.C_SOUND) / I.DT)
     smax = 0.08e-3
-    plan, g = make_case(cen, sen, nt, smax, t0=t0, fwd_tile=fwd_tile, adj_tile=adj_tile)
+    plan, g = make_case(cen, sen, nt, smax, t0=t0, fwd_tile=fwd_tile, adj_tile=adj_tile,
+                        fwd_waves=fwd_waves)
+    assert plan.info()["fwd_waves"] == fwd_waves
     A = I.uniform(1000, seed=9, lo=-0.5, hi=1.0)
     sigma = I.uniform(1000, seed=10, lo=0.3 * smax, hi=smax)
     y, ref = check_forward(plan, g, A, sigma, "point cloud")
     assert np.abs(ref[:, 0]).max() > 0 and np.abs(ref[:, -1]).max() > 0
     delta = I.standard_normal((70, nt), seed=11)
     check_adjoint(plan, g, A, sigma, delta, "point cloud")
+
+
+def test_forward_amplitudes_over_six_decades(toy):
+    """Partial sums are carried in fixed point scaled to each tile's sum of
+    |A_k|: amplitudes of both signs spread log-uniformly over six decades (a
+    few kernels dominate each tile) still meet the bar, and zero amplitudes
+    give an exactly zero trace."""
+    w, plan, g = toy
+    mag = 10.0 ** I.uniform(w.n_kernels, seed=31, lo=-6.0, hi=0.0)
+    sgn = np.where(I.uniform(w.n_kernels, seed=32) < 0.5, -1.0, 1.0)
+    A = (sgn * mag).astype(np.float32)
+    sigma = I.uniform(w.n_kernels, seed=33, lo=0.5 * w.sigma, hi=w.sigma)
+    check_forward(plan, g, A, sigma, "toy, |A| log-uniform over 1e-6..1, random signs")
+    y0 = host(plan.forward(dev(np.zeros(w.n_kernels, np.float32)), dev(sigma)))
+    assert np.all(y0 == 0.0)
+
+
+def test_forward_propagates_non_finite_amplitudes(toy):
+    w, plan, g = toy
+    A = I.phantom(w).copy()
+    A[w.n_kernels // 2] = np.nan
+    y = host(plan.forward(dev(A), dev(np.full(w.n_kernels, w.sigma, np.float32))))
+    assert not np.all(np.isfinite(y))
 
 
 def test_single_kernel_single_sensor():
