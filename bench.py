@@ -39,7 +39,7 @@ MEASURED_TRAFFIC = {
 
 # The same for the ASSA kernels (assa.hip).
 MEASURED_TRAFFIC_ASSA = {
-    "eeda02f9d007075a": {"assa_forward_kernel": 2.839e9, "assa_adjoint_kernel": 0.852e9},
+    "5896f44c6c7ee9c9": {"assa_forward_kernel": 2.839e9, "assa_adjoint_kernel": 0.851e9},
 }
 
 

@@ -14,15 +14,15 @@
 // truncating conversion yields the row (the folded value is >= 0 wherever the
 // row is used, where truncation and floor agree).
 //
-// Forward, fused per (tile, 64 sensors) in one workgroup of four waves:
+// Forward, fused per (tile, 64 sensors) in one workgroup of eight waves:
 //  1. projection P_up: lane = sensor; the waves split the tile's kernels and
-//     add x_i / r_ij into one fine-grid LDS segment per sensor.  The four
+//     add x_i / r_ij into one fine-grid LDS segment per sensor.  The
 //     waves share the segment, so the adds are LDS atomics; they are integer
 //     adds of a fixed-point value (LDS float atomics measured about three times
 //     slower).  The unit of a column is S / 2^30 with S = sum_tile |x| /
 //     r_low, r_low a lower bound of the tile's distances to that sensor: no
 //     partial sum can overflow, and every impulse is resolved to
-//     2^-31 S (about 1e-7 of an impulse for a uniform tile of 256 kernels).
+//     2^-31 S (about 5e-7 of an impulse for a uniform tile of 1024 kernels).
 //     Within a wave each lane owns its column, so the adds are free of bank
 //     conflicts.  The sums are exact and independent of the order of the adds;
 //     after the projection each column is converted to float in place;
@@ -48,8 +48,12 @@
 namespace gpair {
 namespace {
 
-constexpr int kAssaWaves = 4;         // waves per forward workgroup (one sensor group)
-constexpr int kAssaOut = 16;          // coarse samples per wave per convolution pass
+// Waves per forward workgroup (one sensor group).  The projection is latency
+// bound and the segment caps the workgroups per CU, so more waves per segment
+// pay: 8 waves (83 VGPRs, 6 waves per SIMD) ran 12% faster than 4 at the
+// paper shape.
+constexpr int kAssaWaves = 8;
+constexpr int kAssaOut = kWave / kAssaWaves;  // coarse samples per wave per convolution pass
 constexpr int kAssaPass = kAssaWaves * kAssaOut;
 constexpr int kAssaStageRegs = 16;    // floats per thread of an adjoint stage in flight
 constexpr int kPairs = 4;             // kernel-sensor pairs per projection iteration
@@ -331,7 +335,7 @@ __global__ __launch_bounds__(kAssaWaves * kWave) void assa_forward_kernel(
     }
     __syncthreads();
 
-    // 1. Projection: wave w takes a contiguous quarter of the tile's kernels,
+    // 1. Projection: wave w takes a contiguous share of the tile's kernels,
     //    kPairs pairs per iteration in one straight-line block so that their
     //    float64 chains interleave (the chain is latency-bound: 4 pairs per
     //    iteration measured 19% faster than 2, 8 slower again), the next
@@ -363,8 +367,8 @@ __global__ __launch_bounds__(kAssaWaves * kWave) void assa_forward_kernel(
     }
     __syncthreads();
 
-    // 2. Convolution and decimation, 64 coarse samples per round (16 per
-    //    wave), from the fixed-point rows (converted to float in registers),
+    // 2. Convolution and decimation, 64 coarse samples per round (kAssaOut
+    //    per wave), from the fixed-point rows (converted to float in registers),
     //    results in float.  Round r writes rows [64r, 64r + 64) once every
     //    wave has read its inputs; later rounds read rows >= alpha (64r + 64),
     //    so nothing they need is overwritten.
@@ -391,7 +395,7 @@ __global__ __launch_bounds__(kAssaWaves * kWave) void assa_forward_kernel(
       __syncthreads();
     }
 
-    // 3. Flush: wave w adds the rows of sensors w, w + 4, ...; lanes walk the
+    // 3. Flush: wave w adds the rows of sensors w, w + 8, ...; lanes walk the
     //    coarse samples of one sensor (consecutive addresses of y).
     for (int row = wave; row < kWave; row += kAssaWaves) {
       const int jr = sg * kWave + row;
