@@ -14,7 +14,8 @@
 //    therefore decided in float64, as in the float64 reference.
 //  * Tap stage, float32: d_i = d_0 - i Delta, and the Gaussian factor by the
 //    exact recurrence e_{i+1} = e_i q_i, q_{i+1} = q_i rq (two exp2 per pair
-//    instead of one per tap).
+//    instead of one per tap; windows longer than 18 taps re-evaluate e and q
+//    every 16 taps, since the rounding of tap i grows like i^2).
 //  * Forward: one workgroup = one tile of kernels x 64 sensors; lane = sensor,
 //    the kernel loop is wave-uniform (kernel data in scalar registers) and the
 //    workgroup's waves split the tile's kernels.  The waves share one LDS
@@ -115,7 +116,8 @@ __device__ __forceinline__ PairTerms pair_terms(double sx, double sy, double sz,
 // ---------------------------------------------------------------------------
 // Everything the tap loop of one kernel-sensor pair needs.
 struct Taps {
-  float f;       // w * exp(-d0^2 / (2 sigma^2)) with w = A / (2 r)
+  float w;       // A / (2 r)
+  float f;       // w * exp(-d0^2 / (2 sigma^2))
   float q;       // ratio of the second tap's Gaussian factor to the first's
   float d;       // d0 = r - v t of the first tap (m)
   int o;         // first tap's slot in the lane's segment
@@ -132,7 +134,8 @@ __device__ __forceinline__ Taps pair_taps(const double4 &s, const KernelRec &r, 
   // L - 4; the clamp (omax = L - 1 - the samples the caller writes) only keeps
   // LDS accesses in range if that were ever violated.
   t.o = min(max(pt.lo - nb, 0), omax);
-  t.f = (0.5f * r.amp) * pt.rinv * __builtin_amdgcn_exp2f(r.c * t.d * t.d);
+  t.w = (0.5f * r.amp) * pt.rinv;
+  t.f = t.w * __builtin_amdgcn_exp2f(r.c * t.d * t.d);
   t.q = __builtin_amdgcn_exp2f(fmaf(r.k1, t.d, r.k2));
   return t;
 }
@@ -167,14 +170,21 @@ __device__ __forceinline__ void taps_add(int *p, float f, float q, float d, floa
   for (int i = 0; i < NT; ++i) lds_add(p + i * kWave, t[i]);
 }
 
+// The recurrence of a tap loop runs at most this many taps from exactly
+// evaluated factors: the relative error of tap i grows like i^2/2 float32
+// roundings (about 1e-5 after 18 taps, 7e-5 after 48).
+constexpr int kTapRun = 16;
+
 // Taps of one pair whose tap count n is wave-uniform but not known at compile
-// time: a scalar branch to the unrolled form, a loop beyond 18 taps.
-__device__ __forceinline__ void taps_add_n(int n, int *p, float f, float q, float d, float rq,
-                                           float vdt, bool last_ok) {
-  const int nvalid = n - (last_ok ? 0 : 1);
+// time: a scalar branch to the unrolled form; beyond 18 taps a loop that
+// re-evaluates the Gaussian factors every kTapRun taps (rec: the pair's
+// record, read again only there).
+__device__ __forceinline__ void taps_add_n(int n, int *p, const Taps &t, float rq, float vdt,
+                                           float iu, const KernelRec *rec) {
+  const int nvalid = n - (t.last_ok ? 0 : 1);
   switch (n) {
 #define GPAIR_TAPS_CASE(k) \
-  case k: taps_add<k>(p, f, q, d, rq, vdt, nvalid); return;
+  case k: taps_add<k>(p, t.f * iu, t.q, t.d, rq, vdt, nvalid); return;
     GPAIR_TAPS_CASE(1) GPAIR_TAPS_CASE(2) GPAIR_TAPS_CASE(3) GPAIR_TAPS_CASE(4)
     GPAIR_TAPS_CASE(5) GPAIR_TAPS_CASE(6) GPAIR_TAPS_CASE(7) GPAIR_TAPS_CASE(8)
     GPAIR_TAPS_CASE(9) GPAIR_TAPS_CASE(10) GPAIR_TAPS_CASE(11) GPAIR_TAPS_CASE(12)
@@ -183,13 +193,19 @@ __device__ __forceinline__ void taps_add_n(int n, int *p, float f, float q, floa
 #undef GPAIR_TAPS_CASE
     default: break;
   }
-  for (int i = 0; i < n - 1; ++i) {
-    lds_add(p + i * kWave, f * d);
-    d -= vdt;
-    f *= q;
-    q *= rq;
+  const float c = rec->c, k1 = rec->k1, k2 = rec->k2, w = t.w * iu;
+  for (int i0 = 0; i0 < n; i0 += kTapRun) {
+    float d = fmaf(-(float)i0, vdt, t.d);
+    float f = w * __builtin_amdgcn_exp2f(c * d * d);
+    float q = __builtin_amdgcn_exp2f(fmaf(k1, d, k2));
+    const int iend = min(i0 + kTapRun, n);
+    for (int i = i0; i < iend; ++i) {
+      lds_add(p + i * kWave, i < nvalid ? f * d : 0.0f);
+      d -= vdt;
+      f *= q;
+      q *= rq;
+    }
   }
-  lds_add(p + (n - 1) * kWave, last_ok ? f * d : 0.0f);
 }
 
 struct FwdLoop {
@@ -242,12 +258,12 @@ __device__ __forceinline__ void kernel_loop_mixed(const FwdLoop &c, int *col, in
     const int na = ra.ntap, nb = rb.ntap;
     ra = c.krec[min(k + 2, last)];
     rb = c.krec[min(k + 3, last)];
-    taps_add_n(na, col + ta.o * kWave, ta.f * c.iu, ta.q, ta.d, rqa, c.vdt_f, ta.last_ok);
-    taps_add_n(nb, col + tb.o * kWave, tb.f * c.iu, tb.q, tb.d, rqb, c.vdt_f, tb.last_ok);
+    taps_add_n(na, col + ta.o * kWave, ta, rqa, c.vdt_f, c.iu, c.krec + k);
+    taps_add_n(nb, col + tb.o * kWave, tb, rqb, c.vdt_f, c.iu, c.krec + min(k + 1, last));
   }
   if (pend < kend) {
     const Taps t = pair_taps(c.s, ra, c.nb, c.L - 1 - ra.ntap, c.inv_vdt, c.t0_over_dt, c.vdt);
-    taps_add_n(ra.ntap, col + t.o * kWave, t.f * c.iu, t.q, t.d, ra.rq, c.vdt_f, t.last_ok);
+    taps_add_n(ra.ntap, col + t.o * kWave, t, ra.rq, c.vdt_f, c.iu, c.krec + pend);
   }
 }
 
@@ -449,14 +465,22 @@ __device__ __forceinline__ void adjoint_stage(const AdjPair &c, int nsb, float &
     if (NT > 0) {
       gather_taps<(NT > 0 ? NT : 1), SIG>(row, f, q, d0, r.rq, c.vdt_f, nvalid, pA, pS);
     } else {
-      float ff = f, qq = q, d = d0;
-      for (int it = 0; it < nvalid; ++it) {
-        const float pd = row[it] * ff * d;
-        pA += pd;
-        if (SIG) pS = fmaf(pd, d * d, pS);
-        d -= c.vdt_f;
-        ff *= qq;
-        qq *= r.rq;
+      // Any tap count: the Gaussian factors are re-evaluated every kTapRun
+      // taps, as in the forward.
+      const float w = 0.5f * pt.rinv;
+      for (int i0 = 0; i0 < nvalid; i0 += kTapRun) {
+        float d = fmaf(-(float)i0, c.vdt_f, d0);
+        float ff = w * __builtin_amdgcn_exp2f(r.c * d * d);
+        float qq = __builtin_amdgcn_exp2f(fmaf(r.k1, d, r.k2));
+        const int iend = min(i0 + kTapRun, nvalid);
+        for (int it = i0; it < iend; ++it) {
+          const float pd = row[it] * ff * d;
+          pA += pd;
+          if (SIG) pS = fmaf(pd, d * d, pS);
+          d -= c.vdt_f;
+          ff *= qq;
+          qq *= r.rq;
+        }
       }
     }
   }

@@ -110,7 +110,7 @@ def test_adjointness_on_gpu(toy):
 
 
 @pytest.mark.parametrize("fwd_tile,adj_tile,fwd_waves",
-                         [(64, 64, 1), (256, 128, 2), (1024, 256, 4), (64, 256, 4)])
+                         [(64, 64, 1), (256, 128, 2), (1024, 256, 4), (64, 256, 8)])
 def test_ragged_point_cloud_clipped_windows(fwd_tile, adj_tile, fwd_waves):
     """A random point cloud (not a lattice), N_d not a multiple of 64, tiles of
     several sizes (the last one partly filled), 1, 2 or 4 waves splitting each
@@ -157,6 +157,26 @@ def test_forward_propagates_non_finite_amplitudes(toy):
     A[w.n_kernels // 2] = np.nan
     y = host(plan.forward(dev(A), dev(np.full(w.n_kernels, w.sigma, np.float32))))
     assert not np.all(np.isfinite(y))
+
+
+@pytest.mark.parametrize("spread", [False, True])
+def test_wide_kernels_beyond_the_unrolled_tap_counts(spread):
+    """sigma up to 0.3 mm at 25 ns sampling: up to 47 taps per pair, beyond the
+    unrolled forms (18 taps), so the forward and the adjoint take their
+    general tap loops; with a uniform sigma every tile has one tap count, with
+    spread sigma the counts run from 13 to 47 within a tile."""
+    _say(f"case: wide kernels, sigma {'spread' if spread else 'uniform'}")
+    rng = np.random.default_rng(12)
+    cen = rng.uniform(-2e-3, 2e-3, (700, 3)).astype(np.float32)
+    sen = I.fibonacci_hemisphere(90, 15e-3)
+    smax = 0.3e-3
+    plan, g = make_case(cen, sen, 700, smax)
+    assert plan.info()["max_taps"] > 40
+    A = I.uniform(700, seed=13, lo=-0.5, hi=1.0)
+    sigma = (I.uniform(700, seed=14, lo=0.25 * smax, hi=smax) if spread
+             else np.full(700, smax, np.float32))
+    check_forward(plan, g, A, sigma, "wide kernels")
+    check_adjoint(plan, g, A, sigma, I.standard_normal((90, 700), seed=15), "wide kernels")
 
 
 def test_single_kernel_single_sensor():
