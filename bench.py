@@ -39,7 +39,7 @@ MEASURED_TRAFFIC = {
 
 # The same for the ASSA kernels (assa.hip).
 MEASURED_TRAFFIC_ASSA = {
-    "5896f44c6c7ee9c9": {"assa_forward_kernel": 2.839e9, "assa_adjoint_kernel": 0.851e9},
+    "809c3f1e778e69b9": {"assa_forward_kernel": 3.683e9, "assa_adjoint_kernel": 0.843e9},
 }
 
 

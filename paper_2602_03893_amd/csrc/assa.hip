@@ -265,9 +265,14 @@ __device__ __forceinline__ void conv_any(const int *icol, int c0, int nu, int al
 }
 
 // A, KK > 0: the grid (alpha, K) is fixed at compile time (register-window
-// convolution); A = 0: any grid.
+// convolution); A = 0: any grid.  The register budget is that of 7 waves per
+// SIMD (72 VGPRs, a few spills in the convolution), although the segment
+// already caps a CU at 3 workgroups (6 waves per SIMD): the schedule the
+// compiler makes for it ran 14% faster for (3, 12) and 10% for (2, 16) than
+// the unconstrained one (83 and 92 VGPRs) at the paper shape.
 template <int A, int KK>
-__global__ __launch_bounds__(kAssaWaves * kWave) void assa_forward_kernel(
+__global__ __launch_bounds__(kAssaWaves * kWave) __attribute__((amdgpu_waves_per_eu(7)))
+void assa_forward_kernel(
     const KernelRec *__restrict__ krec, AssaFwdArgs a) {
   extern __shared__ float seg[];  // [F][64]: fine row p of sensor column l at p*64 + l
   __shared__ float hqs[kAssaMaxK];
