@@ -35,6 +35,8 @@
 //  * Blocks are remapped so that each of the 8 XCDs works on a contiguous
 //    range of tiles (its L2 then holds that region's kernel records and the
 //    matching residual rows).
+#include <climits>
+
 #include "gpair_internal.h"
 
 namespace gpair {
@@ -491,6 +493,8 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(const double4 *__restric
                                                        AdjArgs a) {
   extern __shared__ float stage[];  // [kAdjSensorsPerStage][L]
   __shared__ int nbs[kAdjSensorsPerStage];
+  __shared__ int4 tapn[BLOCK / 4];   // tap count of each of the tile's kernels
+  __shared__ int order[BLOCK];      // tile kernels by tap count
 
   const int64_t logical = xcd_logical_block(a.nlogical);
   if (logical >= a.nlogical) return;
@@ -498,8 +502,28 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(const double4 *__restric
   const int t = threadIdx.x;
   const int lane = t & (kWave - 1);
   const int wave = t >> 6;
+
+  // Each wave runs the largest tap count of its kernels, so the tile's
+  // kernels are assigned to threads in order of tap count (ties by index):
+  // a wave then mostly holds kernels of one width.  Every kernel is still
+  // summed by one thread with the same operations.  Positions past the
+  // tile's end sort last, so thread t holds a kernel iff t < count.
+  {
+    const int mine = t < T.count ? a.krec[T.start + t].ntap : INT_MAX;
+    reinterpret_cast<int *>(tapn)[t] = mine;
+    __syncthreads();
+    int rank = 0;
+    for (int u4 = 0; u4 < BLOCK / 4; ++u4) {
+      const int4 k = tapn[u4];
+      const int u = 4 * u4;
+      rank += (k.x < mine || (k.x == mine && u < t)) + (k.y < mine || (k.y == mine && u + 1 < t)) +
+              (k.z < mine || (k.z == mine && u + 2 < t)) + (k.w < mine || (k.w == mine && u + 3 < t));
+    }
+    order[rank] = t;
+    __syncthreads();
+  }
   const bool live = t < T.count;
-  const int64_t i = T.start + (live ? t : 0);
+  const int64_t i = T.start + (live ? order[t] : 0);
   const KernelRec r = a.krec[i];
 
   // Tap-count range of the wave's kernels: selects the unrolled gather.
