@@ -162,6 +162,24 @@ void gpair_plan_destroy(gpair_plan p);
 /* Fill *info.  Errors: INVALID_ARG. */
 gpair_status gpair_plan_get_info(gpair_plan p, gpair_plan_info *info);
 
+/*
+ * The binning invariant the operators rely on (no LDS index is clamped): for
+ * a tile with bounding sphere (c_t, rho_t) and a sensor s, the segment starts
+ * at sample nb = floor((|s - c_t| - rho_t)/(v dt) - t0/dt - h_max) - 1, and
+ * every member's window, with the up to two masked padding taps of the
+ * unrolled tap loops, lies in slots [0, segment) of it.  gpair_plan_create
+ * proves this per (tile, sensor) from the sphere bounds and refuses the
+ * geometry (INVALID_ARG) if the margins do not hold.  This host-only call
+ * checks it pair by pair instead, for every member of every forward
+ * (which = 0) or adjoint (which = 1) tile and every sensor, at the widest
+ * admitted window: *min_first = the smallest first-tap slot (>= 0 when the
+ * invariant holds) and *max_last = the largest slot touched (<= the
+ * segment length - 1).  Cost O(n_kernels * n_sensors) on the host threads.
+ * Errors: INVALID_ARG.
+ */
+gpair_status gpair_plan_tiling_slots(gpair_plan p, int32_t which, int64_t *min_first,
+                                     int64_t *max_last);
+
 /* ------------------------------------------------------------------------ */
 /* a1 + a2. Forward operator                                                  */
 /* ------------------------------------------------------------------------ */

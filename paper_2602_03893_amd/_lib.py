@@ -103,6 +103,8 @@ gpair_plan_bind_workspace = _proto("gpair_plan_bind_workspace", c_i32,
                                    [c_vp, c_vp, ctypes.c_size_t, c_vp])
 gpair_plan_destroy = _proto("gpair_plan_destroy", None, [c_vp])
 gpair_plan_get_info = _proto("gpair_plan_get_info", c_i32, [c_vp, ctypes.POINTER(PlanInfo)])
+gpair_plan_tiling_slots = _proto("gpair_plan_tiling_slots", c_i32,
+                                 [c_vp, c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)])
 gpair_forward = _proto("gpair_forward", c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp])
 gpair_adjoint = _proto("gpair_adjoint", c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp])
 gpair_sigma_violations = _proto("gpair_sigma_violations", c_i32,

@@ -142,6 +142,12 @@ gpair_status gpair_plan_get_info(gpair_plan p, gpair_plan_info *info) {
   return GPAIR_OK;
 }
 
+gpair_status gpair_plan_tiling_slots(gpair_plan p, int32_t which, int64_t *min_first,
+                                     int64_t *max_last) {
+  if (!p || !min_first || !max_last || (which != 0 && which != 1)) return GPAIR_ERR_INVALID_ARG;
+  return tiling_slots(p, which, min_first, max_last);
+}
+
 static void timer_begin(gpair_plan p, int which, hipStream_t s) {
   if (p->timing) (void)hipEventRecord(p->ev_start[which][p->ev_head[which]], s);
 }

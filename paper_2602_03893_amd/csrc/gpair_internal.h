@@ -209,6 +209,10 @@ inline double *ws_partials(const gpair_plan_s *p) { return (double *)(p->ws + p-
 
 // Host planner (plan.cpp).
 gpair_status build_plan(const gpair_geometry *g, gpair_plan_s *p);
+// Exhaustive host check of the binning invariant over every (tile member,
+// sensor) pair of the forward (which = 0) or adjoint (1) tiling.
+gpair_status tiling_slots(const gpair_plan_s *p, int which, int64_t *min_first,
+                          int64_t *max_last);
 WorkspaceLayout layout_for(int64_t M, int32_t Nd, size_t nft, size_t nat);
 
 }  // namespace gpair

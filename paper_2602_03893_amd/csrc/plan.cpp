@@ -11,6 +11,7 @@
 // the window, so one short trace segment per (tile, sensor) holds every tap of
 // the tile: that is the binning by sensor-distance shell the kernels use.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -232,7 +233,99 @@ int segment_len(double rho, double inv_vdt, double hmax) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Window half-width (samples) of the widest kernel the records admit: the
+// record builder clamps sigma to sigma_max (1 + 1e-6).
+double hmax_admitted(const gpair_plan_s *p) { return p->hmax * (1.0 + 1e-6); }
+
+// Lower slot of a (tile, sensor) trace segment, exactly as the operators
+// compute it: nb = floor((R - rho) / (v dt) - t0 / dt - h_max) - 1.
+int64_t segment_base(const gpair_plan_s *p, const TileInfo &T, const double *s) {
+  const double dx = s[0] - T.cx, dy = s[1] - T.cy, dz = s[2] - T.cz;
+  const double R = std::sqrt(std::fma(dz, dz, std::fma(dy, dy, dx * dx)));
+  return (int64_t)std::floor((R - T.rho) * p->inv_vdt - p->t0_over_dt - p->hmax) - 1;
+}
+
+// Slot bound of the trace segments (the binning invariant the operators rely
+// on instead of clamping LDS indices).  For a member k of tile T at distance
+// r from sensor s, r lies in [R - rho, R + rho], so its first in-window
+// sample lo = ceil(r/(v dt) - t0/dt - h_k) satisfies lo - nb >= 1, and its
+// last touched sample, with up to two masked padding taps of the unrolled
+// loops, is at most lo + ntap_k + 1 <= r/(v dt) - t0/dt + h_k + 3.  Both are
+// checked here per (tile, sensor) with the widest admitted window and a
+// rounding margin of 1e-6 samples (distances are float64, ~1e-12 samples).
+// Returns the largest slot any pair can touch, or -1 if a lower bound fails.
+int64_t max_slot(const gpair_plan_s *p, const std::vector<TileInfo> &tiles) {
+  const int64_t nt = (int64_t)tiles.size();
+  const int nth = (int)std::min<int64_t>(host_threads(), std::max<int64_t>(1, nt / 256));
+  const double hm = hmax_admitted(p);
+  std::vector<int64_t> worst(nth, 0);
+  std::vector<std::thread> th;
+  for (int t = 0; t < nth; ++t)
+    th.emplace_back([&, t] {
+      int64_t w = 0;
+      for (int64_t ti = nt * t / nth; ti < nt * (t + 1) / nth; ++ti) {
+        const TileInfo &T = tiles[ti];
+        for (int32_t j = 0; j < p->Nd; ++j) {
+          const double *s = &p->host.sens[4 * (size_t)j];
+          const int64_t nb = segment_base(p, T, s);
+          const double dx = s[0] - T.cx, dy = s[1] - T.cy, dz = s[2] - T.cz;
+          const double R = std::sqrt(dx * dx + dy * dy + dz * dz);
+          const double lo_min = std::ceil((R - T.rho) * p->inv_vdt - p->t0_over_dt - hm - 1e-6);
+          const double hi_max =
+              std::floor((R + T.rho) * p->inv_vdt - p->t0_over_dt + hm + 3.0 + 1e-6);
+          if (lo_min - (double)nb < 0.0) {
+            w = -1;
+            break;
+          }
+          w = std::max(w, (int64_t)hi_max - nb);
+        }
+        if (w < 0) break;
+      }
+      worst[t] = w;
+    });
+  for (auto &x : th) x.join();
+  int64_t w = 0;
+  for (int64_t x : worst) {
+    if (x < 0) return -1;
+    w = std::max(w, x);
+  }
+  return w;
+}
+
 }  // namespace
+
+gpair_status tiling_slots(const gpair_plan_s *p, int which, int64_t *min_first,
+                          int64_t *max_last) {
+  const std::vector<TileInfo> &tiles = which == 0 ? p->host.ftiles : p->host.atiles;
+  const double h = hmax_admitted(p);
+  const int64_t ntap = (int64_t)std::floor(2.0 * h) + 1;
+  const int64_t nt = (int64_t)tiles.size();
+  const int nth = (int)std::min<int64_t>(host_threads(), std::max<int64_t>(1, nt / 64));
+  std::vector<int64_t> lo_t(nth, INT64_MAX), hi_t(nth, INT64_MIN);
+  std::vector<std::thread> th;
+  for (int t = 0; t < nth; ++t)
+    th.emplace_back([&, t] {
+      for (int64_t ti = nt * t / nth; ti < nt * (t + 1) / nth; ++ti) {
+        const TileInfo &T = tiles[ti];
+        for (int32_t j = 0; j < p->Nd; ++j) {
+          const double *s = &p->host.sens[4 * (size_t)j];
+          const int64_t nb = segment_base(p, T, s);
+          for (int32_t i = T.start; i < T.start + T.count; ++i) {
+            const double *c = &p->host.kgeo[4 * (size_t)i];
+            const double dx = s[0] - c[0], dy = s[1] - c[1], dz = s[2] - c[2];
+            const double r = std::sqrt(dx * dx + dy * dy + dz * dz);
+            const int64_t lo = (int64_t)std::ceil(r * p->inv_vdt - p->t0_over_dt - h);
+            lo_t[t] = std::min(lo_t[t], lo - nb);
+            hi_t[t] = std::max(hi_t[t], lo + ntap + 1 - nb);
+          }
+        }
+      }
+    });
+  for (auto &x : th) x.join();
+  *min_first = *std::min_element(lo_t.begin(), lo_t.end());
+  *max_last = *std::max_element(hi_t.begin(), hi_t.end());
+  return GPAIR_OK;
+}
 
 WorkspaceLayout layout_for(int64_t M, int32_t Nd, size_t nft, size_t nat) {
   WorkspaceLayout l{};
@@ -373,6 +466,12 @@ gpair_status build_plan(const gpair_geometry *g, gpair_plan_s *p) {
   if ((int64_t)p->La * kAdjSensorsPerStage * 4 > kMaxSegmentBytes) return GPAIR_ERR_INVALID_ARG;
   p->adj_tile = (int32_t)Ta;
   p->max_rho = std::max(max_rho(h.ftiles), max_rho(h.atiles));
+
+  // The binning invariant: every slot a pair can touch lies in its segment.
+  {
+    const int64_t wf = max_slot(p, h.ftiles), wa = max_slot(p, h.atiles);
+    if (wf < 0 || wf > p->Lf - 1 || wa < 0 || wa > p->La - 1) return GPAIR_ERR_INVALID_ARG;
+  }
 
   // Far-field precondition: every kernel at least 10 sigma_max from every
   // sensor.  Tile spheres give a lower bound; members are checked one by one

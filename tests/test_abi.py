@@ -123,3 +123,51 @@ def test_point_cloud_tiles_cover_every_kernel_once():
     assert info.adj_tiles >= 3000 // info.adj_tile
     assert info.max_tile_radius < 4e-3
     _lib.gpair_plan_destroy(h)
+
+
+def _slots(h, which):
+    from paper_2602_03893_amd import _lib
+    lo, hi = ctypes.c_int64(), ctypes.c_int64()
+    assert _lib.gpair_plan_tiling_slots(h, which, ctypes.byref(lo), ctypes.byref(hi)) == 0
+    return lo.value, hi.value
+
+
+@pytest.mark.parametrize("case", ["sparse_cloud", "widest_window", "clipped_ends", "lattice"])
+def test_binning_invariant_holds_pair_by_pair(case):
+    """Every pair's window (with the padding taps of the unrolled loops) lies
+    inside its (tile, sensor) segment, checked pair by pair on the host, for
+    geometries that stress the bound: a sparse point cloud whose tiles have
+    large bounding spheres, sigma_max of 0.4 mm (33 taps), a time origin that
+    cuts windows at both trace ends, and a lattice with the default tiles."""
+    from paper_2602_03893_amd import _lib, inputs as I
+    rng = np.random.default_rng(21)
+    kw = {}
+    if case == "sparse_cloud":
+        cen = rng.uniform(-6e-3, 6e-3, (1500, 3)).astype(np.float32)
+        sen = I.fibonacci_hemisphere(37, 30e-3)
+        kw = dict(nt=2048, fwd_tile=512)
+    elif case == "widest_window":
+        cen = rng.uniform(-1e-3, 1e-3, (900, 3)).astype(np.float32)
+        sen = I.fibonacci_hemisphere(29, 15e-3)
+        kw = dict(nt=1024, smax=0.4e-3)
+    elif case == "clipped_ends":
+        cen = rng.uniform(-1.5e-3, 1.5e-3, (800, 3)).astype(np.float32)
+        sen = I.fibonacci_hemisphere(70, 12e-3)
+        kw = dict(nt=50)
+    else:
+        cen = I.grid_centres(32, 16, 8, 0.1e-3)
+        sen = I.fibonacci_hemisphere(65, 12e-3)
+        kw = dict(nt=1024)
+    g, keep = _geometry(cen, sen, **kw)
+    if case == "clipped_ends":
+        g.t0 = 11e-3 / 1500.0
+    st, h = _create(g)
+    assert st == 0
+    info = _lib.PlanInfo()
+    _lib.gpair_plan_get_info(h, ctypes.byref(info))
+    for which, seg in ((0, info.fwd_segment), (1, info.adj_segment)):
+        lo, hi = _slots(h, which)
+        assert 0 <= lo and hi <= seg - 1, (case, which, lo, hi, seg)
+    assert _lib.gpair_plan_tiling_slots(h, 2, ctypes.byref(ctypes.c_int64()),
+                                        ctypes.byref(ctypes.c_int64())) == -1
+    _lib.gpair_plan_destroy(h)
