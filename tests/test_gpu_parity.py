@@ -247,3 +247,39 @@ def test_paper_scale_sampled():
     efd = np.abs(gS[pick] - fd) / np.maximum(np.abs(fd), 1e-3 * np.abs(fd).max())
     _say(f"  gsigma vs central differences: max rel {efd.max():.3e}")
     assert efd.max() <= 1e-3
+
+
+@pytest.mark.parametrize("spread", [0.0, 0.05])
+def test_paper_scale_at_the_benchmark_sigma(spread):
+    """The configuration the benchmark times: 1024-kernel forward tiles with
+    four waves, sigma = 0.05 mm (9-tap windows, the unrolled forward and
+    gather) uniform or spread by +-5 % (8 or 9 taps: the ninth tap masked per
+    pair, and the adjoint's ranking by tap count).  Forward on 16 sensors,
+    adjoint (A and sigma) on 131,072 kernels."""
+    _say(f"case: paper workload at sigma = 0.05 mm, spread {spread}")
+    w, plan, g = workload_case("paper")
+    info = plan.info()
+    assert info["fwd_tile"] == 1024 and info["fwd_waves"] == 4 and info["adj_tile"] == 256
+    A = I.phantom(w)
+    sigma = np.full(w.n_kernels, w.sigma, np.float32)
+    if spread:
+        sigma = (sigma * I.uniform(w.n_kernels, seed=16, lo=1 - spread, hi=1 + spread))
+        sigma = sigma.astype(np.float32)
+    taps = np.floor(2 * 3.0 * sigma.astype(np.float64) / (w.c_sound * w.dt)) + 1
+    _say(f"  taps per pair: {sorted(set(taps.astype(int).tolist()))}")
+    y = host(plan.forward(dev(A), dev(sigma)))
+    rows = np.random.default_rng(17).choice(w.n_sensors, 16, replace=False)
+    ref = O.forward(g.subset_sensors(rows), A, sigma.astype(np.float64))
+    err = rel_l2(y[rows], ref)
+    _say(f"  forward (16 sensors) rel L2 {err:.3e}")
+    assert np.abs(ref).max() > 0 and err <= TOL
+    delta = I.standard_normal((w.n_sensors, w.n_samples), seed=18)
+    gA, gS = plan.adjoint(dev(0.5 * A + 0.1), dev(sigma), dev(delta))
+    gA, gS = host(gA), host(gS)
+    ks = np.arange(5, w.n_kernels, 64)
+    A2 = (0.5 * A + 0.1).astype(np.float32)
+    rA, rS = O.adjoint(g.subset_kernels(ks), A2[ks], sigma[ks].astype(np.float64),
+                       delta.astype(np.float64))
+    eA, eS = rel_l2(gA[ks], rA), rel_l2(gS[ks], rS)
+    _say(f"  adjoint ({ks.size} kernels) gA {eA:.3e} gsigma {eS:.3e}")
+    assert eA <= TOL and eS <= TOL

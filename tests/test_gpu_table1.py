@@ -48,42 +48,71 @@ def case(name):
     return w, plan, g
 
 
-def test_planar_256_direct_operators():
-    w, plan, g = case("t1_planar_256")
+# sigma of the direct operators per shape: "mixed" = U[0.5, 1] sigma_max (9-17
+# taps, per-pair tap branches), "bench" = 0.05 mm spread by +-5 % (8 or 9 taps,
+# the unrolled loops), "uniform" = 0.05 mm.
+SHAPES = {
+    "t1_planar_64": "mixed", "t1_planar_256": "mixed", "t1_planar_1024": "bench",
+    "t1_hemi_64": "uniform", "t1_hemi_256": "mixed", "t1_hemi_1024": "bench",
+}
+
+
+def sigmas(w, kind, seed):
+    if kind == "mixed":
+        return I.uniform(w.n_kernels, seed=seed, lo=0.5 * w.smax, hi=w.smax)
+    s = np.full(w.n_kernels, w.sigma, np.float32)
+    if kind == "bench":
+        s = (s * I.uniform(w.n_kernels, seed=seed, lo=0.95, hi=1.05)).astype(np.float32)
+    return s
+
+
+def check_direct(w, plan, g, kind, seed):
     A = I.phantom(w)
-    sigma = I.uniform(w.n_kernels, seed=41, lo=0.5 * w.smax, hi=w.smax)
+    sigma = sigmas(w, kind, seed)
     y = host(plan.forward(dev(A), dev(sigma)))
-    rows = np.random.default_rng(42).choice(w.n_sensors, 6, replace=False)
+    rows = np.random.default_rng(seed + 1).choice(w.n_sensors, 6, replace=False)
     ref = O.forward(g.subset_sensors(rows), A, sigma.astype(np.float64))
     err = rel_l2(y[rows], ref)
-    _say(f"  forward (6 sensors) rel L2 {err:.3e}")
+    _say(f"  direct forward ({kind} sigma, 6 sensors) rel L2 {err:.3e}")
     assert np.abs(ref).max() > 0 and err <= TOL
-    delta = I.standard_normal((w.n_sensors, w.n_samples), seed=43)
+    delta = I.standard_normal((w.n_sensors, w.n_samples), seed=seed + 2)
     gA, gS = plan.adjoint(dev(A), dev(sigma), dev(delta))
     gA, gS = host(gA), host(gS)
     ks = np.arange(7, w.n_kernels, 1024)
     rA, rS = O.adjoint(g.subset_kernels(ks), A[ks], sigma[ks].astype(np.float64),
                        delta.astype(np.float64))
     eA, eS = rel_l2(gA[ks], rA), rel_l2(gS[ks], rS)
-    _say(f"  adjoint ({ks.size} kernels) gA {eA:.3e} gsigma {eS:.3e}")
+    _say(f"  direct adjoint ({ks.size} kernels) gA {eA:.3e} gsigma {eS:.3e}")
     assert eA <= TOL and eS <= TOL
 
 
-def test_hemisphere_64_assa_operators():
-    w, plan, g = case("t1_hemi_64")
+def check_assa(w, plan, g, seed):
     grid = plan.assa_grid(w.sigma)
     _say(f"  ASSA grid {grid}")
     x = I.phantom(w)
     y = host(plan.assa_forward(dev(x), w.sigma))
-    rows = np.random.default_rng(44).choice(w.n_sensors, 6, replace=False)
+    rows = np.random.default_rng(seed).choice(w.n_sensors, 6, replace=False)
     ref = S.forward(g.subset_sensors(rows), x.astype(np.float64), w.sigma)
     err = rel_l2(y[rows], ref)
     _say(f"  ASSA forward (6 sensors) rel L2 {err:.3e}")
     assert np.abs(ref).max() > 0 and err <= TOL
-    delta = I.standard_normal((w.n_sensors, w.n_samples), seed=45)
+    delta = I.standard_normal((w.n_sensors, w.n_samples), seed=seed + 1)
     got = host(plan.assa_adjoint(w.sigma, dev(delta)))
     ks = np.arange(3, w.n_kernels, 512)
     ref = S.adjoint(g.subset_kernels(ks), w.sigma, delta.astype(np.float64))
     err = rel_l2(got[ks], ref)
     _say(f"  ASSA back-projection ({ks.size} kernels) rel L2 {err:.3e}")
     assert err <= TOL
+
+
+@pytest.mark.parametrize("name", list(SHAPES))
+def test_simulation_study_shape(name):
+    """Both backends at one of the six shapes of the simulation study."""
+    w, plan, g = case(name)
+    seed = 40 + 10 * list(SHAPES).index(name)
+    try:
+        check_direct(w, plan, g, SHAPES[name], seed)
+        check_assa(w, plan, g, seed + 5)
+    finally:
+        del plan
+        torch.cuda.empty_cache()
