@@ -501,6 +501,25 @@ gpair_status gpair_assa_forward(gpair_plan p, const float *x, double sigma, floa
 gpair_status gpair_assa_adjoint(gpair_plan p, double sigma, const float *delta, float *g,
                                 void *work, size_t work_bytes, gpair_stream stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid hipMalloc):
+ * gpair_assa_adjoint without the work argument.  The convolved residual is
+ * kept in a fixed device array of this library instead,
+ * gpair_assa_static_scratch_bytes() bytes (64 MiB, enough for
+ * n_sensors * alpha * n_samples <= 16,777,216: the paper-scale shape needs
+ * 12,582,912), which each GPU holds from the first call on it until the
+ * process ends.  The plan's device must be current.  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (several streams or
+ * threads) race, so serialise them.  The call itself allocates nothing.
+ *  delta, g  as gpair_assa_adjoint (g overwritten).
+ * Errors: INVALID_ARG, SIGMA_RANGE, WORKSPACE (the residual would not fit the
+ * array; nothing is launched), HIP.
+ */
+gpair_status gpair_assa_adjoint_static(gpair_plan p, double sigma, const float *delta, float *g,
+                                       gpair_stream stream);
+size_t gpair_assa_static_scratch_bytes(void);
+
 /* ------------------------------------------------------------------------ */
 /* f2. The paper's full objective: NPC, VCR, CAWR                             */
 /* ------------------------------------------------------------------------ */

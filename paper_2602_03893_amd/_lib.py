@@ -140,6 +140,9 @@ gpair_assa_workspace_size = _proto("gpair_assa_workspace_size", c_i32,
 gpair_assa_forward = _proto("gpair_assa_forward", c_i32, [c_vp, c_vp, c_dbl, c_vp, c_vp])
 gpair_assa_adjoint = _proto("gpair_assa_adjoint", c_i32,
                             [c_vp, c_dbl, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp])
+gpair_assa_adjoint_static = _proto("gpair_assa_adjoint_static", c_i32,
+                                   [c_vp, c_dbl, c_vp, c_vp, c_vp])
+gpair_assa_static_scratch_bytes = _proto("gpair_assa_static_scratch_bytes", ctypes.c_size_t, [])
 gpair_npc_map = _proto("gpair_npc_map", c_i32, [c_i64, c_vp, c_dbl, c_vp, c_vp])
 gpair_npc_grad = _proto("gpair_npc_grad", c_i32, [c_i64, c_vp, c_vp, c_dbl, c_vp, c_vp])
 gpair_vcr_workspace_size = _proto("gpair_vcr_workspace_size", c_i32,

@@ -204,6 +204,18 @@ class Plan:
                                       _stream()), "gpair_assa_adjoint")
         return g
 
+    def assa_adjoint_static(self, sigma, delta, out=None):
+        """assa_adjoint with the library's fixed device buffer as its work
+        space (gpair_assa_adjoint_static: the call allocates nothing; `out`
+        must be given for that)."""
+        pd = _dev(delta, "delta", self.n_sensors * self.n_samples, device=self.device)
+        g = out if out is not None else torch.empty(self.n_kernels, dtype=torch.float32,
+                                                    device=self.device)
+        pg = _dev(g, "g", self.n_kernels, device=self.device)
+        check(_lib.gpair_assa_adjoint_static(self._h, float(sigma), pd, pg, _stream()),
+              "gpair_assa_adjoint_static")
+        return g
+
     def sigma_violations(self):
         n = ctypes.c_int64()
         check(_lib.gpair_sigma_violations(self._h, ctypes.byref(n), _stream()),
