@@ -8,8 +8,9 @@ which holds none of the method's arithmetic and is imported by the tests, not by
 this package.
 
 Contents
- - ``ops``      forward / adjoint / sigma-gradient of the direct operator (C,
-                float64, OpenMP), Eq. (single_forward) with the n_sigma window.
+ - ``ops``      forward / adjoint / sigma-gradient / centre gradient of the
+                direct operator (C, float64, OpenMP), Eq. (single_forward) with
+                the n_sigma window.
  - ``physics``  closed forms of the Methods derivation (sphere integral,
                 two-term pressure) and their numerical Poisson-integral checks.
  - ``solvers``  relative residual, power iteration, projected gradient and Adam
@@ -27,6 +28,9 @@ Pins (what each function is checked against, in ``tests/``):
  - ``ops.adjoint``   the dot-product test <A x, y> = <x, A^T y> against the pinned
                      forward; gA and gsigma against central finite differences of
                      the pinned forward.
+ - ``ops.adjoint_centres``  central differences of the pinned forward in float32
+                     centres; torch autograd of an independent torch
+                     formulation over the same windows.
  - ``physics``       Gauss-Legendre quadrature of the surface integral and a
                      numerical derivative of Eq. (pa_wave).
  - ``solvers.pgd``   converges to scipy's NNLS solution (a different algorithm).

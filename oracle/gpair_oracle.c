@@ -123,6 +123,53 @@ void oracle_adjoint(int64_t m, const float *cx, const float *cy,
 }
 
 /*
+ * Gradient with respect to the kernel centres (learnable centres, named as
+ * future work in the paper's Discussion): the derivative of
+ * Eq. (single_forward) through r = |s - c_k| at fixed window membership (the
+ * indicator is locally constant in c_k, as it is in sigma_k):
+ *   dp/dr  = A e / (2r) * (1 - d^2 / sigma^2 - d / r),
+ *   dr/dc_k = (c_k - s) / r,
+ *   gc[k]  = sum_j sum_{n in W} delta_j[n] dp/dr (c_k - s_j) / r.
+ * delta float64 [nd][nt]; gc float64 [m][3], overwritten.
+ */
+void oracle_adjoint_centres(int64_t m, const float *cx, const float *cy,
+                            const float *cz, const double *amp,
+                            const double *sigma, int64_t nd,
+                            const float *sensors, int64_t nt, double dt,
+                            double t0, double v, double nsig,
+                            const double *delta, double *gc) {
+  int64_t k;
+#pragma omp parallel for schedule(static)
+  for (k = 0; k < m; ++k) {
+    double sg = (double)sigma[k];
+    double half = nsig * sg;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t j = 0; j < nd; ++j) {
+      const float *s = sensors + 3 * j;
+      double r = pair_distance(s, cx[k], cy[k], cz[k]);
+      int64_t lo, hi;
+      candidate_range(r, half, v, dt, t0, nt, &lo, &hi);
+      double sum = 0.0;
+      for (int64_t n = lo; n <= hi; ++n) {
+        double t = t0 + (double)n * dt;
+        double d = r - v * t;
+        if (fabs(d) <= half) {
+          double e = exp(-(d * d) / (2.0 * sg * sg));
+          double dpdr = amp[k] * e / (2.0 * r) * (1.0 - d * d / (sg * sg) - d / r);
+          sum += delta[j * nt + n] * dpdr;
+        }
+      }
+      acc[0] += sum * ((double)cx[k] - (double)s[0]) / r;
+      acc[1] += sum * ((double)cy[k] - (double)s[1]) / r;
+      acc[2] += sum * ((double)cz[k] - (double)s[2]) / r;
+    }
+    gc[3 * k] = acc[0];
+    gc[3 * k + 1] = acc[1];
+    gc[3 * k + 2] = acc[2];
+  }
+}
+
+/*
  * Number of in-window taps of every pair, summed (the work count the
  * benchmark reports), and the number of pairs with at least one tap.
  */

@@ -11,7 +11,9 @@ Definitions (arXiv 2602.03893, Methods):
    inclusive window |d| <= n_sigma*sigma_k ("3 sigma principle"), summed over
    kernels, sampled at t0 + n*dt for n in [0, n_samples);
  - adjoint: the transpose of that linear map ("Adjoint Operator" subsection);
- - sigma-gradient: d/dsigma of Eq. (single_forward), A d^3 e / (2 r sigma^3).
+ - sigma-gradient: d/dsigma of Eq. (single_forward), A d^3 e / (2 r sigma^3);
+ - centre gradient: d/dc_k of Eq. (single_forward) through r = |s - c_k|
+   (learnable centres, the paper's stated future work), window held fixed.
 """
 import ctypes
 import os
@@ -44,6 +46,10 @@ def _load():
     lib.oracle_adjoint.argtypes = [_i64, _f32p, _f32p, _f32p, _f64p, _f64p,
                                    _i64, _f32p, _i64, _dbl, _dbl, _dbl, _dbl,
                                    _f64p, _f64p, ctypes.c_void_p]
+    lib.oracle_adjoint_centres.restype = None
+    lib.oracle_adjoint_centres.argtypes = [_i64, _f32p, _f32p, _f32p, _f64p, _f64p,
+                                           _i64, _f32p, _i64, _dbl, _dbl, _dbl, _dbl,
+                                           _f64p, _f64p]
     lib.oracle_count_taps.restype = None
     lib.oracle_count_taps.argtypes = [_i64, _f32p, _f32p, _f32p, _f64p, _i64,
                                       _f32p, _i64, _dbl, _dbl, _dbl, _dbl,
@@ -129,6 +135,22 @@ def adjoint(g: Geometry, amp, sigma, delta, want_sigma=True):
                        g.n_sigma, d, ga,
                        gs.ctypes.data_as(ctypes.c_void_p) if gs is not None else None)
     return ga, gs
+
+
+def adjoint_centres(g: Geometry, amp, sigma, delta):
+    """gc float64 (M, 3): the gradient of <A(x; c), delta> with respect to the
+    kernel centres, window membership held fixed."""
+    lib = _load()
+    a = _vec(amp, g.n_kernels, "amp")
+    s = _vec(sigma, g.n_kernels, "sigma")
+    d = np.ascontiguousarray(np.asarray(delta, dtype=np.float64))
+    if d.shape != (g.n_sensors, g.n_samples):
+        raise ValueError(f"delta: expected {(g.n_sensors, g.n_samples)}, got {d.shape}")
+    gc = np.empty((g.n_kernels, 3), dtype=np.float64)
+    lib.oracle_adjoint_centres(g.n_kernels, g.cx, g.cy, g.cz, a, s, g.n_sensors,
+                               g.sensors, g.n_samples, g.dt, g.t0, g.c_sound,
+                               g.n_sigma, d, gc)
+    return gc
 
 
 def count_taps(g: Geometry, sigma):
