@@ -180,6 +180,16 @@ gpair_status gpair_plan_get_info(gpair_plan p, gpair_plan_info *info);
 gpair_status gpair_plan_tiling_slots(gpair_plan p, int32_t which, int64_t *min_first,
                                      int64_t *max_last);
 
+/*
+ * The float32 window filter of the direct operators (see gpair_forward):
+ * *float64_blocks = the number of adjoint tiles whose pairs are all decided
+ * in float64 because a sensor is too close for the filter's error bound
+ * (within 4 tile radii, or a radius too large for the guard), and
+ * *max_steps = the most fixed-point steps any other tile runs for its
+ * distance offsets.  Host-only.  Errors: INVALID_ARG.
+ */
+gpair_status gpair_plan_filter_stats(gpair_plan p, int64_t *float64_blocks, int32_t *max_steps);
+
 /* ------------------------------------------------------------------------ */
 /* a1 + a2. Forward operator                                                  */
 /* ------------------------------------------------------------------------ */
@@ -586,6 +596,21 @@ gpair_status gpair_cawr_rate(int64_t t, double eta_min, double eta_max, int64_t 
 #define GPAIR_TIMER_KINDS 4
 
 #define GPAIR_TIMER_SLOTS 64   /* launches remembered per kind              */
+
+/*
+ * Issue-rate probe of one vector instruction (the ceilings the operators'
+ * roofline is stated against): blocks x 256 threads, each running 8
+ * independent dependency chains of `iters` x 8 steps of
+ *   kind 0: float32 FMA (v_fma_f32)      kind 1: float64 FMA (v_fma_f64)
+ *   kind 2: float32 exp2 (v_exp_f32)     kind 3: float32 1/sqrt (v_rsq_f32)
+ *   kind 4: float64 1/sqrt (v_rsq_f64)
+ * then one float per thread written to out (device float32 [blocks * 256];
+ * its value is meaningless).  *per_wave (host) receives the number of probed
+ * instructions each wave issues; divide waves x per_wave by the kernel's time.
+ * Errors: INVALID_ARG, HIP.
+ */
+gpair_status gpair_peak_probe(int32_t kind, int32_t blocks, int32_t iters, float *out,
+                              int64_t *per_wave, gpair_stream stream);
 
 /*
  * enable != 0: record a pair of HIP events around the main kernel of each

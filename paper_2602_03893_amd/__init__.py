@@ -16,6 +16,7 @@ _LAZY = {
     "npc_grad": ("api", "npc_grad"),
     "vcr": ("api", "vcr"),
     "cawr_rate": ("api", "cawr_rate"),
+    "peak_probe": ("api", "peak_probe"),
     "GpairError": ("_lib", "GpairError"),
     "GpairForward": ("autograd", "GpairForward"),
     "gpair_forward": ("autograd", "gpair_forward"),

@@ -105,6 +105,8 @@ gpair_plan_destroy = _proto("gpair_plan_destroy", None, [c_vp])
 gpair_plan_get_info = _proto("gpair_plan_get_info", c_i32, [c_vp, ctypes.POINTER(PlanInfo)])
 gpair_plan_tiling_slots = _proto("gpair_plan_tiling_slots", c_i32,
                                  [c_vp, c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)])
+gpair_plan_filter_stats = _proto("gpair_plan_filter_stats", c_i32,
+                                 [c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i32)])
 gpair_forward = _proto("gpair_forward", c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp])
 gpair_adjoint = _proto("gpair_adjoint", c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp])
 gpair_sigma_violations = _proto("gpair_sigma_violations", c_i32,
@@ -143,6 +145,8 @@ gpair_assa_adjoint = _proto("gpair_assa_adjoint", c_i32,
 gpair_assa_adjoint_static = _proto("gpair_assa_adjoint_static", c_i32,
                                    [c_vp, c_dbl, c_vp, c_vp, c_vp])
 gpair_assa_static_scratch_bytes = _proto("gpair_assa_static_scratch_bytes", ctypes.c_size_t, [])
+gpair_peak_probe = _proto("gpair_peak_probe", c_i32,
+                          [c_i32, c_i32, c_i32, c_vp, ctypes.POINTER(c_i64), c_vp])
 gpair_npc_map = _proto("gpair_npc_map", c_i32, [c_i64, c_vp, c_dbl, c_vp, c_vp])
 gpair_npc_grad = _proto("gpair_npc_grad", c_i32, [c_i64, c_vp, c_vp, c_dbl, c_vp, c_vp])
 gpair_vcr_workspace_size = _proto("gpair_vcr_workspace_size", c_i32,

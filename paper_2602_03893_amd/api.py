@@ -105,6 +105,13 @@ class Plan:
         check(_lib.gpair_plan_get_info(self._h, ctypes.byref(i)), "gpair_plan_get_info")
         return {f: getattr(i, f) for f, _ in i._fields_}
 
+    def filter_stats(self):
+        """(adjoint tiles decided in float64 throughout, most filter steps)."""
+        n, k = ctypes.c_int64(), ctypes.c_int32()
+        check(_lib.gpair_plan_filter_stats(self._h, ctypes.byref(n), ctypes.byref(k)),
+              "gpair_plan_filter_stats")
+        return int(n.value), int(k.value)
+
     # -- operators --------------------------------------------------------
     def forward(self, A, sigma, out=None):
         """y (N_d, N_t) float32 = A(x; sigma)."""
@@ -354,3 +361,32 @@ def cawr_rate(t, eta_min, eta_max, T0, Tmult=1):
 
 __all__ = ["Plan", "pgd_update", "adam_update", "npc_map", "npc_grad", "vcr", "cawr_rate",
            "GpairError"]
+
+
+PEAK_PROBES = {0: "v_fma_f32", 1: "v_fma_f64", 2: "v_exp_f32", 3: "v_rsq_f32", 4: "v_rsq_f64"}
+
+
+def peak_probe(kind, blocks=8192, iters=256, repeats=5):
+    """Issue rate of one vector instruction (gpair_peak_probe): returns
+    (wave64 instructions per second, kernel ms), the best of `repeats` timed
+    launches after one warm-up, timed with events on the current stream."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    out = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+    per_wave = ctypes.c_int64()
+
+    def launch():
+        check(_lib.gpair_peak_probe(int(kind), int(blocks), int(iters), _dev(out, "out"),
+                                    ctypes.byref(per_wave), _stream()), "gpair_peak_probe")
+
+    launch()
+    best = None
+    for _ in range(repeats):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        launch()
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    waves = blocks * 256 // 64
+    return waves * per_wave.value / (best * 1e-3), best

@@ -1,6 +1,7 @@
 // api.cpp -- extern "C" entry points of libgpair (declared in include/gpair.h).
 // Host-side argument validation, then kernel launches on the caller's stream.
 // No C++ exception crosses the boundary.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -91,13 +92,26 @@ gpair_status gpair_plan_bind_workspace(gpair_plan p, void *workspace, size_t wor
   } catch (...) {
     return GPAIR_ERR_INVALID_ARG;
   }
-  parallel_ranges(p->M, [&](int64_t b, int64_t e) {
-    for (int64_t i = b; i < e; ++i) {
-      KernelRec r{};
-      r.cx = h.kgeo[4 * i];
-      r.cy = h.kgeo[4 * i + 1];
-      r.cz = h.kgeo[4 * i + 2];
-      rec[i] = r;
+  // Geometry fields: the caller's float32 centre, and its float32 offset from
+  // the float32-rounded centre of its adjoint tile (the filter's reference
+  // block), a float32 subtraction exactly as written.
+  const std::vector<TileInfo> &blocks = h.atiles;
+  parallel_ranges((int64_t)blocks.size(), [&](int64_t b0, int64_t b1) {
+    for (int64_t b = b0; b < b1; ++b) {
+      const TileInfo &B = blocks[b];
+      const float bx = (float)B.cx, by = (float)B.cy, bz = (float)B.cz;
+      for (int64_t i = B.start; i < (int64_t)B.start + B.count; ++i) {
+        KernelRec r{};
+        r.fcx = (float)h.kgeo[4 * i];
+        r.fcy = (float)h.kgeo[4 * i + 1];
+        r.fcz = (float)h.kgeo[4 * i + 2];
+        const float dx = r.fcx - bx, dy = r.fcy - by, dz = r.fcz - bz;
+        r.dx = dx;
+        r.dy = dy;
+        r.dz = dz;
+        r.dd = (float)((double)dx * dx + (double)dy * dy + (double)dz * dz);
+        rec[i] = r;
+      }
     }
   });
   up(p->lay.krec, rec.data(), rec.size() * sizeof(KernelRec));
@@ -146,6 +160,19 @@ gpair_status gpair_plan_tiling_slots(gpair_plan p, int32_t which, int64_t *min_f
                                      int64_t *max_last) {
   if (!p || !min_first || !max_last || (which != 0 && which != 1)) return GPAIR_ERR_INVALID_ARG;
   return tiling_slots(p, which, min_first, max_last);
+}
+
+gpair_status gpair_plan_filter_stats(gpair_plan p, int64_t *float64_blocks, int32_t *max_steps) {
+  if (!p || !float64_blocks || !max_steps) return GPAIR_ERR_INVALID_ARG;
+  int64_t n = 0;
+  int32_t k = 0;
+  for (const TileInfo &B : p->host.atiles) {
+    if (B.filter_steps < 0) ++n;
+    else k = std::max(k, B.filter_steps);
+  }
+  *float64_blocks = n;
+  *max_steps = k;
+  return GPAIR_OK;
 }
 
 static void timer_begin(gpair_plan p, int which, hipStream_t s) {

@@ -134,17 +134,21 @@ __host__ __device__ inline TileInfo merge_tiles(const TileInfo &a, const TileInf
 // and the tile's sum of |x| into its TileInfo (the fixed-point scale).
 __global__ __launch_bounds__(256) void assa_prep_kernel(const float *__restrict__ x,
                                                         const int32_t *__restrict__ perm,
-                                                        KernelRec *__restrict__ rec,
+                                                        AssaRec *__restrict__ rec,
                                                         TileInfo *__restrict__ tiles) {
   __shared__ float part[256 / kWave];
   TileInfo &T = tiles[blockIdx.x];
   const int start = T.start, count = T.count;
   float acc = 0.0f;
   for (int i = threadIdx.x; i < count; i += 256) {
-    KernelRec &r = rec[start + i];
+    AssaRec &r = rec[start + i];
     const float v = x[perm[start + i]];
+    const double cx = (double)r.fcx, cy = (double)r.fcy, cz = (double)r.fcz;
+    r.cx = cx;
+    r.cy = cy;
+    r.cz = cz;
     r.amp = v;
-    r.h = fma(r.cz, r.cz, fma(r.cy, r.cy, r.cx * r.cx));  // |c|^2
+    r.cc = fma(cz, cz, fma(cy, cy, cx * cx));  // |c|^2
     acc += fabsf(v);
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
@@ -196,9 +200,9 @@ __device__ __forceinline__ int round_half_up(float v) {
   return n;
 }
 
-__device__ __forceinline__ Impulse impulse(const Lane &l, const KernelRec &r, int F,
+__device__ __forceinline__ Impulse impulse(const Lane &l, const AssaRec &r, int F,
                                            double ku) {
-  const Dist d = pair_dist(l.m2x, l.m2y, l.m2z, r.cx, r.cy, r.cz, l.s2 + r.h);
+  const Dist d = pair_dist(l.m2x, l.m2y, l.m2z, r.cx, r.cy, r.cz, l.s2 + r.cc);
   const int p1 = (int)fma(d.r, ku, l.cst);  // |value| < 1e9 (checked on the host)
   const bool in = (unsigned)(p1 - l.plo) < (unsigned)l.pspan;
   Impulse o;
@@ -273,7 +277,7 @@ __device__ __forceinline__ void conv_any(const int *icol, int c0, int nu, int al
 template <int A, int KK>
 __global__ __launch_bounds__(kAssaWaves * kWave) __attribute__((amdgpu_waves_per_eu(7)))
 void assa_forward_kernel(
-    const KernelRec *__restrict__ krec, AssaFwdArgs a) {
+    const AssaRec *__restrict__ krec, AssaFwdArgs a) {
   extern __shared__ float seg[];  // [F][64]: fine row p of sensor column l at p*64 + l
   __shared__ float hqs[kAssaMaxK];
 
@@ -348,7 +352,7 @@ void assa_forward_kernel(
     if (k0 < k1) {
       static_assert(kPairs == 4, "the loop below is written out for 4 pairs");
       const int last = k1 - 1;
-      KernelRec ra = krec[k0], rb = krec[min(k0 + 1, last)], rc = krec[min(k0 + 2, last)],
+      AssaRec ra = krec[k0], rb = krec[min(k0 + 1, last)], rc = krec[min(k0 + 2, last)],
                 rd = krec[min(k0 + 3, last)];
       int k = k0;
       for (; k + 3 < k1; k += 4) {
@@ -450,7 +454,7 @@ __global__ __launch_bounds__(256) void assa_dconv_kernel(AssaConvArgs a) {
 // Adjoint, step 2: back-projection g_i = sum_j delta_conv_j[k_ij] / r_ij.
 // ---------------------------------------------------------------------------
 struct AssaAdjArgs {
-  const KernelRec *krec;
+  const AssaRec *krec;
   const TileInfo *tiles;
   const int32_t *perm;
   const float *dconv;
@@ -533,7 +537,7 @@ __global__ __launch_bounds__(BLOCK) void assa_adjoint_kernel(const double4 *__re
   const int t = threadIdx.x;
   const bool live0 = t < T.count, live1 = t + BLOCK < T.count;
   const int64_t i0 = T.start + (live0 ? t : 0), i1 = T.start + (live1 ? t + BLOCK : 0);
-  const KernelRec r0 = a.krec[i0], r1 = a.krec[i1];
+  const AssaRec r0 = a.krec[i0], r1 = a.krec[i1];
   const int pmax = a.Fa - 1;
   const double ax = -2.0 * r0.cx, ay = -2.0 * r0.cy, az = -2.0 * r0.cz;
   const double ac2 = fma(r0.cz, r0.cz, fma(r0.cy, r0.cy, r0.cx * r0.cx));
@@ -672,7 +676,7 @@ size_t assa_work_bytes(const gpair_plan_s *p, const AssaGrid &g) {
 
 hipError_t launch_assa_prep(const gpair_plan_s *p, const float *x, hipStream_t s) {
   const unsigned int grid = (unsigned int)p->host.ftiles.size();
-  assa_prep_kernel<<<grid, 256, 0, s>>>(x, ws_perm(p), ws_krec(p), ws_ftiles(p));
+  assa_prep_kernel<<<grid, 256, 0, s>>>(x, ws_perm(p), (AssaRec *)ws_krec(p), ws_ftiles(p));
   return hipGetLastError();
 }
 
@@ -700,13 +704,13 @@ hipError_t launch_assa_forward(const gpair_plan_s *p, const AssaGrid &g, float *
   const unsigned int grid = xcd_blocks(a.nlogical);
   const int block = kAssaWaves * kWave;
   if (g.alpha == 3 && g.K == 12)
-    assa_forward_kernel<3, 12><<<grid, block, lds, s>>>(ws_krec(p), a);
+    assa_forward_kernel<3, 12><<<grid, block, lds, s>>>((const AssaRec *)ws_krec(p), a);
   else if (g.alpha == 2 && g.K == 16)
-    assa_forward_kernel<2, 16><<<grid, block, lds, s>>>(ws_krec(p), a);
+    assa_forward_kernel<2, 16><<<grid, block, lds, s>>>((const AssaRec *)ws_krec(p), a);
   else if (g.alpha == 4 && g.K == 12)
-    assa_forward_kernel<4, 12><<<grid, block, lds, s>>>(ws_krec(p), a);
+    assa_forward_kernel<4, 12><<<grid, block, lds, s>>>((const AssaRec *)ws_krec(p), a);
   else
-    assa_forward_kernel<0, 0><<<grid, block, lds, s>>>(ws_krec(p), a);
+    assa_forward_kernel<0, 0><<<grid, block, lds, s>>>((const AssaRec *)ws_krec(p), a);
   return hipGetLastError();
 }
 
@@ -730,7 +734,7 @@ hipError_t launch_assa_dconv(const gpair_plan_s *p, const AssaGrid &g, const flo
 hipError_t launch_assa_adjoint(const gpair_plan_s *p, const AssaGrid &g, const float *dconv,
                                float *out, hipStream_t s) {
   AssaAdjArgs a{};
-  a.krec = ws_krec(p);
+  a.krec = (const AssaRec *)ws_krec(p);
   a.tiles = ws_atiles(p);
   a.perm = ws_perm(p);
   a.dconv = dconv;

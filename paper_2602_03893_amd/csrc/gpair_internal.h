@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cstdint>
 #include <memory>
 #include <thread>
@@ -59,7 +60,10 @@ void parallel_ranges(int64_t n, F f) {
 }
 
 // Bounding sphere and kernel range of one tile (a compact spatial block of
-// kernels, consecutive in the plan's permuted kernel order).
+// kernels, consecutive in the plan's permuted kernel order).  Adjoint tiles
+// are nested in forward tiles; they are also the reference blocks of the
+// float32 distance filter (the float32-rounded centre of an adjoint tile is
+// the reference point of its members).
 struct alignas(16) TileInfo {
   double cx, cy, cz;  // sphere centre (m)
   double rho;         // sphere radius (m): every member is within rho
@@ -67,32 +71,58 @@ struct alignas(16) TileInfo {
   int32_t count;      // number of members (<= the tile size)
   float asum;         // per-call scratch of the ASSA forward: sum of |x| over
                       // the members (forward tiles only)
-  int32_t pad1;
+  union {
+    int32_t first_block;   // forward tiles: index of the first adjoint tile inside
+    int32_t filter_steps;  // adjoint tiles: fixed-point steps of the float32
+                           // window filter, or -1: every pair in float64
+  };
 };
 static_assert(sizeof(TileInfo) == 48, "TileInfo layout");
 
 // One 64-byte record per kernel (permuted order), read by the forward as a
-// single scalar load.  The centre is written once when the plan is bound; the
-// coefficients are rebuilt on every operator call from (A, sigma).
-// With Delta = v*dt and c = -log2(e) / (2 sigma^2):
-//   exp(-d^2/(2 sigma^2)) = exp2(c d^2);
-//   the ratio of consecutive taps (d -> d - Delta) is q(d) = exp2(k2 + k1 d)
-//   with k1 = -2 c Delta, k2 = c Delta^2, and q itself is multiplied by
-//   rq = exp2(2 c Delta^2) from one tap to the next.
+// single scalar load.  The geometry fields (d*, dd, fc*) are written once
+// when the plan is bound; the coefficients are rebuilt on every operator
+// call from (A, sigma).  Offsets along a window are in samples: with
+// Delta = v dt, h = n_sigma sigma / Delta and c = -log2(e) Delta^2 /
+// (2 sigma^2),
+//   exp(-d^2/(2 sigma^2)) = exp2(c u^2) for d = u Delta;
+//   the ratio of consecutive taps (u -> u - 1) is q(u) = exp2(k1 u + c) with
+//   k1 = -2c, and q itself is multiplied by rq = exp2(2c) from one tap to
+//   the next.
 struct alignas(64) KernelRec {
-  double cx, cy, cz;  // centre (m), float64 copy of the caller's float32
-  double h;           // n_sigma sigma_k / Delta: window half-width in samples
-                      // (the ASSA forward stores |c|^2 here instead)
-  float amp;          // A_k
-  float c;            // -log2(e) / (2 sigma_k^2)
-  float k1;           // -2 c Delta
-  float k2;           // c Delta^2
-  float rq;           // exp2(2 c Delta^2)
-  int32_t ntap;       // floor(2 h) + 1: most samples a window can hold
-  double hlast;       // (ntap - 1) - h: tap ntap-1 is in the window iff the
-                      // first tap's offset nc - lo is >= hlast
+  float dx, dy, dz;  // float32 centre minus the float32 reference point of
+                     // its adjoint tile (a float32 subtraction)
+  float dd;          // |(dx, dy, dz)|^2
+  float hf;          // h (float32)
+  float H;           // (ntap - 1) - 2h: tap ntap-1 is in the window iff the
+                     // first tap's offset minus h is >= H
+  float amp;         // A_k
+  float c;           // -log2(e) Delta^2 / (2 sigma_k^2)
+  float k1;          // -2 c
+  float rq;          // exp2(2 c)
+  int32_t ntap;      // floor(2 h) + 1: most samples a window can hold
+  float fcz;         // the caller's float32 centre (z)
+  double h;          // n_sigma sigma_k / Delta (float64, the exact path)
+  float fcx, fcy;    // the caller's float32 centre (x, y)
 };
 static_assert(sizeof(KernelRec) == 64, "KernelRec layout");
+
+// The same 64 bytes as the ASSA operators use them (rebuilt by the ASSA
+// prep on every call; the geometry fields are shared with KernelRec).
+struct alignas(64) AssaRec {
+  float dx, dy, dz, dd;  // geometry (unused by ASSA)
+  double cx, cy;         // float64 copy of the float32 centre
+  double cz;
+  float amp;             // x_k
+  float fcz;             // geometry
+  double cc;             // |c|^2
+  float fcx, fcy;        // geometry
+};
+static_assert(sizeof(AssaRec) == 64, "AssaRec layout");
+static_assert(offsetof(AssaRec, fcz) == offsetof(KernelRec, fcz) &&
+                  offsetof(AssaRec, fcx) == offsetof(KernelRec, fcx) &&
+                  offsetof(AssaRec, dd) == offsetof(KernelRec, dd),
+              "shared geometry fields");
 
 constexpr int kWave = 64;
 constexpr int kAdjSensorsPerStage = 64; // sensors staged per LDS refill
@@ -141,6 +171,17 @@ struct gpair_plan_s {
 };
 
 namespace gpair {
+
+// The float32 window filter of the operators for a reference block of
+// radius rho (about its float32-rounded centre) seen from sensors at
+// distance >= R: the number of fixed-point steps for the distance offset
+// that brings its truncation below kFilterIterTol samples, or -1 when the
+// filter's error bound is not below kFilterGuard / 2 (then the operators
+// decide every pair of the block in float64).
+constexpr double kFilterGuard = 0x1p-13;  // samples
+constexpr double kFilterIterTol = 1e-6;   // samples
+constexpr int kFilterMaxSteps = 8;
+int filter_steps(double R, double rho, double inv_vdt, double hmax);
 
 // Kernel launchers (operators.hip, vector_ops.hip).  All return hipSuccess or
 // the launch error.

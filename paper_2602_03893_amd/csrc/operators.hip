@@ -7,31 +7,45 @@
 // Adjoint: its transpose, plus the sigma-derivative of Eq. (single_forward).
 //
 // Work decomposition (VALU-bound; no MFMA: nothing here is a contraction).
-//  * Pair stage, float64: r = |s - c| (float64 difference of float32
-//    coordinates, float32 rsq seed + one float64 Newton step), pulse centre
-//    in samples nc = (r - v t0)/(v dt), first in-window sample lo =
-//    ceil(nc - h) with h = n_sigma sigma / (v dt).  Window membership is
-//    therefore decided in float64, as in the float64 reference.
-//  * Tap stage, float32: d_i = d_0 - i Delta, and the Gaussian factor by the
-//    exact recurrence e_{i+1} = e_i q_i, q_{i+1} = q_i rq (two exp2 per pair
-//    instead of one per tap; windows longer than 18 taps re-evaluate e and q
-//    every 16 taps, since the rounding of tap i grows like i^2).
+//  * Pair stage.  A kernel k of reference block B (an adjoint tile, of
+//    float32-rounded centre c_B) at offset dk = c_k - c_B, seen from sensor s
+//    with u = s - c_B and R = |u| (float64, once per block and sensor), has
+//    r^2 - R^2 = D = |dk|^2 - 2 u.dk, so its distance offset dr = r - R
+//    solves dr = (D - dr^2) / (2R): a few float32 fixed-point steps from
+//    dr = D / (2R), converging by a factor ~rho_B/R per step.  The pulse
+//    position in samples relative to the segment base, z = X + dr/(v dt) - h
+//    (X = R/(v dt) - t0/dt - nb, split into an integer and a float32
+//    fraction), then gives the first in-window sample (ceil z) and the
+//    first tap's offset from the pulse centre.  This is the float32 window
+//    filter.  Its error is bounded at set-up (block_lane) below half of
+//    kGuard; a pair whose z lies within kGuard of a decision boundary (an
+//    integer, or the last tap's threshold) is decided again from the
+//    caller's float32 coordinates in float64, exactly as the float64
+//    reference does, so window membership is the float64 decision.  Blocks
+//    too close to a sensor for the bound use the float64 decision for every
+//    pair.
+//  * Tap stage, float32, offsets in samples: u_i = u_0 - i, and the
+//    Gaussian factor by the exact recurrence e_{i+1} = e_i q_i,
+//    q_{i+1} = q_i rq, so a pair costs two v_exp_f32 instead of one per tap
+//    (windows longer than 18 taps re-evaluate e and q every 16 taps, since
+//    the rounding of tap i grows like i^2).
 //  * Forward: one workgroup = one tile of kernels x 64 sensors; lane = sensor,
 //    the kernel loop is wave-uniform (kernel data in scalar registers) and the
-//    workgroup's waves split the tile's kernels.  The waves share one LDS
-//    trace segment per sensor over the tile's time shell, into which taps go
-//    as 32-bit fixed-point integer adds (ds_add_u32 issues without waiting,
-//    where a float add or a read-modify-write waits for LDS every tap).  The
-//    fixed-point unit is per sensor: 2^-30 of a bound on any sum the tile can
-//    put into one sample (sum_k |A_k| * sigma_max e^{-1/2} / (2 r_low)), so no
-//    sum can overflow and each tap is rounded to 2^-31 of that bound.  At the
-//    end the segment goes back to float32 and is added to y with one
-//    coalesced float atomic per sample (tile-sensor partial sums).
+//    workgroup's waves take the tile's reference blocks.  The waves share one
+//    LDS trace segment per sensor over the tile's time shell, into which taps
+//    go as 32-bit fixed-point integer adds (ds_add_u32 issues without
+//    waiting, where a float add or a read-modify-write waits for LDS every
+//    tap).  The fixed-point unit is per sensor: 2^-30 of a bound on any sum
+//    the tile can put into one sample (sum_k |A_k| * sigma_max e^{-1/2} /
+//    (2 r_low)), so no sum can overflow and each tap is rounded to 2^-31 of
+//    that bound.  At the end the segment goes back to float32 and is added
+//    to y with one coalesced float atomic per sample (tile-sensor partial
+//    sums).
 //  * Adjoint: one workgroup = one tile of kernels; lane = kernel, the sensor
 //    loop is uniform.  For each stage of 64 sensors the residual over the
-//    tile's time shell is staged in LDS; every lane gathers its taps from it.
-//    Per-lane sums go from float32 (within a stage) to float64 (across
-//    stages); no atomics.
+//    tile's time shell and the filter's per-sensor constants are staged in
+//    LDS; every lane gathers its taps from it.  Per-lane sums go from float32
+//    (within a stage) to float64 (across stages); no atomics.
 //  * Blocks are remapped so that each of the 8 XCDs works on a contiguous
 //    range of tiles (its L2 then holds that region's kernel records and the
 //    matching residual rows).
@@ -44,6 +58,10 @@ namespace {
 
 constexpr double kLog2e = 1.4426950408889634074;
 
+// Guard of the float32 window filter (samples): the planner admits a block
+// to the filter only when the filter's error bound is below kGuard / 2.
+constexpr float kGuard = (float)kFilterGuard;
+
 __device__ __forceinline__ int64_t xcd_logical_block(int64_t nlogical) {
   const int64_t per = (nlogical + kXcds - 1) / kXcds;
   const int64_t b = blockIdx.x;
@@ -53,6 +71,15 @@ __device__ __forceinline__ int64_t xcd_logical_block(int64_t nlogical) {
 inline unsigned int xcd_grid(int64_t nlogical) {
   const int64_t per = (nlogical + kXcds - 1) / kXcds;
   return (unsigned int)(per * kXcds);
+}
+
+__device__ __forceinline__ int wave_min(int x) {
+  for (int off = 32; off > 0; off >>= 1) x = min(x, __shfl_xor(x, off, kWave));
+  return x;
+}
+__device__ __forceinline__ int wave_max(int x) {
+  for (int off = 32; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off, kWave));
+  return x;
 }
 
 // ---------------------------------------------------------------------------
@@ -71,46 +98,99 @@ __global__ __launch_bounds__(256) void prep_kernel(
     atomicAdd(viol, 1ULL);
     s = (s > smax_eff) ? smax_eff : ((s > 0.0) ? s : smax_eff);
   }
-  const double c = -kLog2e / (2.0 * s * s);
-  const double h = nsig * s / vdt;
-  KernelRec &r = rec[i];  // the centre fields were written at plan binding
-  r.h = h;
+  const double su = s / vdt;                // sigma in samples
+  const double c = -kLog2e / (2.0 * su * su);
+  const double h = nsig * su;
+  const int32_t ntap = (int32_t)floor(2.0 * h) + 1;
+  KernelRec &r = rec[i];  // the geometry fields were written at plan binding
+  r.hf = (float)h;
+  r.H = (float)((double)(ntap - 1) - 2.0 * h);
   r.amp = a;
   r.c = (float)c;
-  r.k1 = (float)(-2.0 * c * vdt);
-  r.k2 = (float)(c * vdt * vdt);
-  r.rq = (float)exp2(2.0 * c * vdt * vdt);
-  r.ntap = (int32_t)floor(2.0 * h) + 1;
-  r.hlast = (double)(r.ntap - 1) - h;
+  r.k1 = (float)(-2.0 * c);
+  r.rq = (float)exp2(2.0 * c);
+  r.ntap = ntap;
+  r.h = h;
 }
 
 // ---------------------------------------------------------------------------
-// Pair stage shared by both operators (float64 distance and window).
+// Pair stage shared by both operators.
 // ---------------------------------------------------------------------------
-struct PairTerms {
-  double fr;    // nc - lo in (h - 1, h]: offset of the first tap, in samples
-  int lo;       // first in-window sample index
-  float rinv;   // 1/r (float32 rsq seed)
+// Constants of the float32 filter for one (reference block, sensor).
+struct BlockLane {
+  float m2ux, m2uy, m2uz;  // -2 (s - c_B)
+  float inv2R;             // 1 / (2R)
+  float Rf;                // R
+  float Xf;                // X - Xi, X = R/(v dt) - t0/dt - nb
+  int Xi;                  // floor(X)
 };
 
-__device__ __forceinline__ PairTerms pair_terms(double sx, double sy, double sz,
-                                                double cx, double cy, double cz,
-                                                double h, double inv_vdt,
-                                                double t0_over_dt) {
-  const double ex = sx - cx, ey = sy - cy, ez = sz - cz;
-  const double r2 = fma(ez, ez, fma(ey, ey, ex * ex));
-  const float y0 = __builtin_amdgcn_rsqf((float)r2);
-  const double y0d = (double)y0;
-  const double r0 = r2 * y0d;                  // ~r to float32 accuracy
-  const double res = fma(-r0, r0, r2);         // r2 - r0^2
-  const double r = fma(res, 0.5 * y0d, r0);    // one Newton step: ~1e-15 rel
+// Fills bl for the sensor at s (double4: x, y, z, |s|^2) and the block B
+// (its float32-rounded centre is the reference point).  The number of
+// fixed-point steps, or -1 (every pair in float64), is the block's
+// filter_steps, set by the planner from its closest sensor so that the
+// forward and the adjoint run the same arithmetic for every pair.
+__device__ __forceinline__ void block_lane(const double4 &s, const TileInfo &B, int nb,
+                                           double inv_vdt, double t0_over_dt, BlockLane &bl) {
+  const float bx = (float)B.cx, by = (float)B.cy, bz = (float)B.cz;
+  const double ux = s.x - (double)bx, uy = s.y - (double)by, uz = s.z - (double)bz;
+  const double R = sqrt(fma(uz, uz, fma(uy, uy, ux * ux)));
+  const double X = fma(R, inv_vdt, -t0_over_dt) - (double)nb;
+  const double Xi = floor(X);
+  bl.m2ux = (float)(-2.0 * ux);
+  bl.m2uy = (float)(-2.0 * uy);
+  bl.m2uz = (float)(-2.0 * uz);
+  bl.inv2R = (float)(0.5 / R);
+  bl.Rf = (float)R;
+  bl.Xf = (float)(X - Xi);
+  bl.Xi = (int)Xi;
+}
+
+// One pair's window: first tap's slot o (relative to the segment base nb),
+// offset d0 of the first tap from the pulse centre (samples, in (h-1, h]),
+// whether tap ntap-1 is in the window, and 1/r.
+struct PairW {
+  float d0;
+  float rinv;
+  int o;
+  bool last_ok;
+};
+
+// The float32 filter; returns true when a decision is within kGuard of its
+// boundary (then the caller decides again with pair_exact).
+__device__ __forceinline__ bool pair_filter(const BlockLane &bl, int kit, float dx, float dy,
+                                            float dz, float dd, float hf, float H,
+                                            float inv_vdt_f, PairW &p) {
+  const float D = fmaf(bl.m2ux, dx, fmaf(bl.m2uy, dy, fmaf(bl.m2uz, dz, dd)));
+  float dr = D * bl.inv2R;
+  for (int it = 0; it < kit; ++it) dr = fmaf(-dr, dr, D) * bl.inv2R;
+  const float zf = fmaf(dr, inv_vdt_f, bl.Xf - hf);
+  const float cz = ceilf(zf);
+  const float e = zf - cz;  // in (-1, 0]
+  p.o = bl.Xi + (int)cz;
+  p.d0 = e + hf;
+  p.last_ok = e >= H;
+  p.rinv = __builtin_amdgcn_rcpf(bl.Rf + dr);
+  const float m = fminf(fminf(fabsf(e), fabsf(e + 1.0f)), fabsf(e - H));
+  return m < kGuard;
+}
+
+// The float64 decision: r from the caller's float32 coordinates, the first
+// in-window sample lo = ceil((r - v t0)/(v dt) - h), as in the reference
+// definition.  RINV: also set 1/r (otherwise the filter's value is kept).
+template <bool RINV>
+__device__ __forceinline__ void pair_exact(const double4 &s, float fcx, float fcy, float fcz,
+                                           double h, int ntap, int nb, double inv_vdt,
+                                           double t0_over_dt, PairW &p) {
+  const double ex = s.x - (double)fcx, ey = s.y - (double)fcy, ez = s.z - (double)fcz;
+  const double r = sqrt(fma(ez, ez, fma(ey, ey, ex * ex)));
   const double nc = fma(r, inv_vdt, -t0_over_dt);
   const double lo = ceil(nc - h);
-  PairTerms t;
-  t.fr = nc - lo;
-  t.lo = (int)lo;
-  t.rinv = y0;
-  return t;
+  const double fr = nc - lo;
+  p.o = (int)lo - nb;
+  p.d0 = (float)fr;
+  p.last_ok = fr >= (double)(ntap - 1) - h;
+  if (RINV) p.rinv = (float)(1.0 / r);
 }
 
 // ---------------------------------------------------------------------------
@@ -118,27 +198,39 @@ __device__ __forceinline__ PairTerms pair_terms(double sx, double sy, double sz,
 // ---------------------------------------------------------------------------
 // Everything the tap loop of one kernel-sensor pair needs.
 struct Taps {
-  float w;       // A / (2 r)
-  float f;       // w * exp(-d0^2 / (2 sigma^2))
+  float w;       // A / (2 r) Delta, in fixed-point units
+  float f;       // w * exp2(c d0^2)
   float q;       // ratio of the second tap's Gaussian factor to the first's
-  float d;       // d0 = r - v t of the first tap (m)
+  float d;       // d0 (samples)
   int o;         // first tap's slot in the lane's segment
   bool last_ok;  // tap ntap-1 is inside the window
 };
 
-__device__ __forceinline__ Taps pair_taps(const double4 &s, const KernelRec &r, int nb, int omax,
-                                          double inv_vdt, double t0_over_dt, double vdt) {
-  const PairTerms pt = pair_terms(s.x, s.y, s.z, r.cx, r.cy, r.cz, r.h, inv_vdt, t0_over_dt);
+struct FwdLoop {
+  const KernelRec *krec;
+  double4 s;
+  BlockLane bl;
+  int kit, nb;
+  double inv_vdt, t0_over_dt;
+  float inv_vdt_f;
+  float iuw;  // fixed-point units per unit of A/r d/Delta: 2^30/B * Delta/2
+};
+
+template <bool EXACT>
+__device__ __forceinline__ Taps pair_taps(const FwdLoop &c, const KernelRec &r) {
+  PairW p;
+  if (EXACT) {
+    pair_exact<true>(c.s, r.fcx, r.fcy, r.fcz, r.h, r.ntap, c.nb, c.inv_vdt, c.t0_over_dt, p);
+  } else if (pair_filter(c.bl, c.kit, r.dx, r.dy, r.dz, r.dd, r.hf, r.H, c.inv_vdt_f, p)) {
+    pair_exact<false>(c.s, r.fcx, r.fcy, r.fcz, r.h, r.ntap, c.nb, c.inv_vdt, c.t0_over_dt, p);
+  }
   Taps t;
-  t.d = (float)(pt.fr * vdt);
-  t.last_ok = pt.fr >= r.hlast;
-  // By construction of nb and L every tap slot o + i (i < ntap) is at most
-  // L - 4; the clamp (omax = L - 1 - the samples the caller writes) only keeps
-  // LDS accesses in range if that were ever violated.
-  t.o = min(max(pt.lo - nb, 0), omax);
-  t.w = (0.5f * r.amp) * pt.rinv;
+  t.d = p.d0;
+  t.o = p.o;
+  t.last_ok = p.last_ok;
+  t.w = (p.rinv * r.amp) * c.iuw;
   t.f = t.w * __builtin_amdgcn_exp2f(r.c * t.d * t.d);
-  t.q = __builtin_amdgcn_exp2f(fmaf(r.k1, t.d, r.k2));
+  t.q = __builtin_amdgcn_exp2f(fmaf(r.k1, t.d, r.c));
   return t;
 }
 
@@ -156,12 +248,12 @@ __device__ __forceinline__ void lds_add(int *p, float v) {
 // NT - 2, so only the last three can be outside).
 template <int NT>
 __device__ __forceinline__ void taps_add(int *p, float f, float q, float d, float rq,
-                                         float vdt, int nvalid) {
+                                         int nvalid) {
   float t[NT];
 #pragma unroll
   for (int i = 0; i < NT; ++i) {
     t[i] = f * d;
-    d -= vdt;
+    d -= 1.0f;
     f *= q;
     q *= rq;
   }
@@ -181,12 +273,12 @@ constexpr int kTapRun = 16;
 // time: a scalar branch to the unrolled form; beyond 18 taps a loop that
 // re-evaluates the Gaussian factors every kTapRun taps (rec: the pair's
 // record, read again only there).
-__device__ __forceinline__ void taps_add_n(int n, int *p, const Taps &t, float rq, float vdt,
-                                           float iu, const KernelRec *rec) {
+__device__ __forceinline__ void taps_add_n(int n, int *p, const Taps &t, float rq,
+                                           const KernelRec *rec) {
   const int nvalid = n - (t.last_ok ? 0 : 1);
   switch (n) {
 #define GPAIR_TAPS_CASE(k) \
-  case k: taps_add<k>(p, t.f * iu, t.q, t.d, rq, vdt, nvalid); return;
+  case k: taps_add<k>(p, t.f, t.q, t.d, rq, nvalid); return;
     GPAIR_TAPS_CASE(1) GPAIR_TAPS_CASE(2) GPAIR_TAPS_CASE(3) GPAIR_TAPS_CASE(4)
     GPAIR_TAPS_CASE(5) GPAIR_TAPS_CASE(6) GPAIR_TAPS_CASE(7) GPAIR_TAPS_CASE(8)
     GPAIR_TAPS_CASE(9) GPAIR_TAPS_CASE(10) GPAIR_TAPS_CASE(11) GPAIR_TAPS_CASE(12)
@@ -195,85 +287,96 @@ __device__ __forceinline__ void taps_add_n(int n, int *p, const Taps &t, float r
 #undef GPAIR_TAPS_CASE
     default: break;
   }
-  const float c = rec->c, k1 = rec->k1, k2 = rec->k2, w = t.w * iu;
+  const float c = rec->c, k1 = rec->k1;
   for (int i0 = 0; i0 < n; i0 += kTapRun) {
-    float d = fmaf(-(float)i0, vdt, t.d);
-    float f = w * __builtin_amdgcn_exp2f(c * d * d);
-    float q = __builtin_amdgcn_exp2f(fmaf(k1, d, k2));
+    float d = t.d - (float)i0;
+    float f = t.w * __builtin_amdgcn_exp2f(c * d * d);
+    float q = __builtin_amdgcn_exp2f(fmaf(k1, d, c));
     const int iend = min(i0 + kTapRun, n);
     for (int i = i0; i < iend; ++i) {
       lds_add(p + i * kWave, i < nvalid ? f * d : 0.0f);
-      d -= vdt;
+      d -= 1.0f;
       f *= q;
       q *= rq;
     }
   }
 }
 
-struct FwdLoop {
-  const KernelRec *krec;
-  double4 s;
-  int nb, L, omax;
-  double inv_vdt, t0_over_dt, vdt;
-  float vdt_f, iu;
-};
-
-// The kernel loop of one wave over records [k0, kend) of its tile when every
-// kernel of the tile has NT - 2 .. NT taps.  Kernels go in pairs: both pair
-// stages sit in one straight-line block, so their float64 chains interleave,
-// and the records of the next pair are fetched meanwhile (clamped to the last
-// record).  (Four per iteration need 130 VGPRs and run slower.)
-template <int NT>
+// The kernel loop of one wave over records [k0, kend) of one reference
+// block when every kernel of the tile has NT - 2 .. NT taps.  Kernels go in
+// pairs: both pair stages sit in one straight-line block, so their chains
+// interleave, and the records of the next pair are fetched meanwhile
+// (clamped to the last record).
+template <int NT, bool EXACT>
 __device__ __forceinline__ void kernel_loop(const FwdLoop &c, int *col, int k0, int kend) {
   if (k0 >= kend) return;
   const int last = kend - 1;
   const int pend = k0 + ((kend - k0) & ~1);
   KernelRec ra = c.krec[k0], rb = c.krec[min(k0 + 1, last)];
   for (int k = k0; k < pend; k += 2) {
-    const Taps ta = pair_taps(c.s, ra, c.nb, c.omax, c.inv_vdt, c.t0_over_dt, c.vdt);
-    const Taps tb = pair_taps(c.s, rb, c.nb, c.omax, c.inv_vdt, c.t0_over_dt, c.vdt);
+    const Taps ta = pair_taps<EXACT>(c, ra);
+    const Taps tb = pair_taps<EXACT>(c, rb);
     const float rqa = ra.rq, rqb = rb.rq;
     const int nva = ra.ntap - (ta.last_ok ? 0 : 1), nvb = rb.ntap - (tb.last_ok ? 0 : 1);
     ra = c.krec[min(k + 2, last)];
     rb = c.krec[min(k + 3, last)];
-    taps_add<NT>(col + ta.o * kWave, ta.f * c.iu, ta.q, ta.d, rqa, c.vdt_f, nva);
-    taps_add<NT>(col + tb.o * kWave, tb.f * c.iu, tb.q, tb.d, rqb, c.vdt_f, nvb);
+    taps_add<NT>(col + ta.o * kWave, ta.f, ta.q, ta.d, rqa, nva);
+    taps_add<NT>(col + tb.o * kWave, tb.f, tb.q, tb.d, rqb, nvb);
   }
   if (pend < kend) {
-    const Taps t = pair_taps(c.s, ra, c.nb, c.omax, c.inv_vdt, c.t0_over_dt, c.vdt);
-    taps_add<NT>(col + t.o * kWave, t.f * c.iu, t.q, t.d, ra.rq, c.vdt_f,
-                 ra.ntap - (t.last_ok ? 0 : 1));
+    const Taps t = pair_taps<EXACT>(c, ra);
+    taps_add<NT>(col + t.o * kWave, t.f, t.q, t.d, ra.rq, ra.ntap - (t.last_ok ? 0 : 1));
   }
 }
 
 // The same loop for a tile whose kernels differ in width by more than two
 // taps: each pair branches on its own tap count.
-__device__ __forceinline__ void kernel_loop_mixed(const FwdLoop &c, int *col, int k0, int kend) {
+template <bool EXACT>
+__device__ __forceinline__ void kernel_loop_mixed(const FwdLoop &c, int *col, int k0,
+                                                  int kend) {
   if (k0 >= kend) return;
   const int last = kend - 1;
   const int pend = k0 + ((kend - k0) & ~1);
   KernelRec ra = c.krec[k0], rb = c.krec[min(k0 + 1, last)];
   for (int k = k0; k < pend; k += 2) {
-    const Taps ta = pair_taps(c.s, ra, c.nb, c.L - 1 - ra.ntap, c.inv_vdt, c.t0_over_dt, c.vdt);
-    const Taps tb = pair_taps(c.s, rb, c.nb, c.L - 1 - rb.ntap, c.inv_vdt, c.t0_over_dt, c.vdt);
+    const Taps ta = pair_taps<EXACT>(c, ra);
+    const Taps tb = pair_taps<EXACT>(c, rb);
     const float rqa = ra.rq, rqb = rb.rq;
     const int na = ra.ntap, nb = rb.ntap;
     ra = c.krec[min(k + 2, last)];
     rb = c.krec[min(k + 3, last)];
-    taps_add_n(na, col + ta.o * kWave, ta, rqa, c.vdt_f, c.iu, c.krec + k);
-    taps_add_n(nb, col + tb.o * kWave, tb, rqb, c.vdt_f, c.iu, c.krec + min(k + 1, last));
+    taps_add_n(na, col + ta.o * kWave, ta, rqa, c.krec + k);
+    taps_add_n(nb, col + tb.o * kWave, tb, rqb, c.krec + min(k + 1, last));
   }
   if (pend < kend) {
-    const Taps t = pair_taps(c.s, ra, c.nb, c.L - 1 - ra.ntap, c.inv_vdt, c.t0_over_dt, c.vdt);
-    taps_add_n(ra.ntap, col + t.o * kWave, t, ra.rq, c.vdt_f, c.iu, c.krec + pend);
+    const Taps t = pair_taps<EXACT>(c, ra);
+    taps_add_n(ra.ntap, col + t.o * kWave, t, ra.rq, c.krec + pend);
+  }
+}
+
+template <bool EXACT>
+__device__ __forceinline__ void block_loops(const FwdLoop &c, int *col, int k0, int k1,
+                                            int nt_unrolled) {
+  switch (nt_unrolled) {
+#define GPAIR_FWD_CASE(n) \
+  case n: kernel_loop<n, EXACT>(c, col, k0, k1); break;
+    GPAIR_FWD_CASE(2) GPAIR_FWD_CASE(3) GPAIR_FWD_CASE(4) GPAIR_FWD_CASE(5)
+    GPAIR_FWD_CASE(6) GPAIR_FWD_CASE(7) GPAIR_FWD_CASE(8) GPAIR_FWD_CASE(9)
+    GPAIR_FWD_CASE(10) GPAIR_FWD_CASE(11) GPAIR_FWD_CASE(12) GPAIR_FWD_CASE(13)
+    GPAIR_FWD_CASE(14) GPAIR_FWD_CASE(15) GPAIR_FWD_CASE(16) GPAIR_FWD_CASE(17)
+    GPAIR_FWD_CASE(18)
+#undef GPAIR_FWD_CASE
+    default: kernel_loop_mixed<EXACT>(c, col, k0, k1); break;
   }
 }
 
 struct FwdArgs {
   const double4 *sens;
   const TileInfo *tiles;
+  const TileInfo *blocks;  // adjoint tiles: the reference blocks
   float *y;
   int64_t nlogical;
+  int32_t ntiles, nblocks;
   int32_t Nd, Nt, nsg, L;
   double inv_vdt, t0_over_dt, hmax, vdt;
   double peak;      // bound of |A/(2r) d e^{-d^2/2 sigma^2}| r / |A| over sigma <= sigma_max
@@ -330,7 +433,6 @@ __global__ __launch_bounds__(WAVES * kWave) void forward_kernel(
   const double r_low = fmax(R - T.rho, a.min_dist);
   const double bound = (double)asum * a.peak / r_low;
   const float unit = (float)(bound * 0x1p-30);
-  const float iu = bound > 0.0 ? (float)(0x1p30 / bound) : 0.0f;
   __syncthreads();  // the segment is zero
 
   int *const col = seg + lane;
@@ -338,29 +440,20 @@ __global__ __launch_bounds__(WAVES * kWave) void forward_kernel(
   c.krec = krec;
   c.s = s;
   c.nb = nb;
-  c.L = a.L;
   c.inv_vdt = a.inv_vdt;
   c.t0_over_dt = a.t0_over_dt;
-  c.vdt = a.vdt;
-  c.vdt_f = (float)a.vdt;
-  c.iu = iu;
-  const int per = (T.count + WAVES - 1) / WAVES;
-  const int k0 = T.start + wave * per;
-  const int k1 = min(T.start + T.count, k0 + per);
-  if (nmin >= nmax - 2 && nmax >= 2 && nmax <= 18) {
-    c.omax = a.L - 1 - nmax;
-    switch (nmax) {
-#define GPAIR_FWD_CASE(n) \
-  case n: kernel_loop<n>(c, col, k0, k1); break;
-      GPAIR_FWD_CASE(2) GPAIR_FWD_CASE(3) GPAIR_FWD_CASE(4) GPAIR_FWD_CASE(5)
-      GPAIR_FWD_CASE(6) GPAIR_FWD_CASE(7) GPAIR_FWD_CASE(8) GPAIR_FWD_CASE(9)
-      GPAIR_FWD_CASE(10) GPAIR_FWD_CASE(11) GPAIR_FWD_CASE(12) GPAIR_FWD_CASE(13)
-      GPAIR_FWD_CASE(14) GPAIR_FWD_CASE(15) GPAIR_FWD_CASE(16) GPAIR_FWD_CASE(17)
-      default: kernel_loop<18>(c, col, k0, k1); break;
-#undef GPAIR_FWD_CASE
-    }
-  } else {
-    kernel_loop_mixed(c, col, k0, k1);
+  c.inv_vdt_f = (float)a.inv_vdt;
+  c.iuw = bound > 0.0 ? (float)(0x1p30 / bound * 0.5 * a.vdt) : 0.0f;
+  const int nt_unrolled = (nmin >= nmax - 2 && nmax >= 2 && nmax <= 18) ? nmax : 0;
+  const int bend = tile + 1 < a.ntiles ? a.tiles[tile + 1].first_block : a.nblocks;
+  for (int b = T.first_block + wave; b < bend; b += WAVES) {
+    const TileInfo B = a.blocks[b];
+    block_lane(s, B, nb, a.inv_vdt, a.t0_over_dt, c.bl);
+    c.kit = B.filter_steps;
+    if (c.kit < 0)
+      block_loops<true>(c, col, B.start, B.start + B.count, nt_unrolled);
+    else
+      block_loops<false>(c, col, B.start, B.start + B.count, nt_unrolled);
   }
   __syncthreads();
 
@@ -409,23 +502,13 @@ struct AdjArgs {
 // +13% adjoint time at 64 sensors, -2% at 1024 with sigma spread by 5%).
 constexpr int kAdjRankMinSensors = 256;
 
-__device__ __forceinline__ int wave_min(int x) {
-  for (int off = 32; off > 0; off >>= 1) x = min(x, __shfl_xor(x, off, kWave));
-  return x;
-}
-__device__ __forceinline__ int wave_max(int x) {
-  for (int off = 32; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off, kWave));
-  return x;
-}
-
 // Gather the taps of one kernel-sensor pair from a staged residual row (row
 // points at the pair's first sample): NT samples of which the first nvalid
 // are in the window (only the last three can be outside).  All reads are
 // issued first.
 template <int NT, bool SIG>
 __device__ __forceinline__ void gather_taps(const float *row, float f, float q, float d,
-                                            float rq, float vdt, int nvalid, float &pA,
-                                            float &pS) {
+                                            float rq, int nvalid, float &pA, float &pS) {
   float dl[NT];
 #pragma unroll
   for (int i = 0; i < NT; ++i) dl[i] = row[i];
@@ -437,7 +520,7 @@ __device__ __forceinline__ void gather_taps(const float *row, float f, float q, 
     const float pd = dl[i] * f * d;
     pA += pd;
     if (SIG) pS = fmaf(pd, d * d, pS);
-    d -= vdt;
+    d -= 1.0f;
     f *= q;
     q *= rq;
   }
@@ -448,9 +531,12 @@ struct AdjPair {
   const KernelRec *r;
   const float *stage;
   const int *nbs;
-  int L, omax, j0;
-  double inv_vdt, t0_over_dt, vdt;
-  float vdt_f;
+  const float4 *su;  // per staged sensor: -2u (x, y, z), 1/(2R)
+  const float4 *sv;  // per staged sensor: R, Xf, Xi (bits), unused
+  int L, j0;
+  int kit;           // the tile's filter steps, or -1 (every pair in float64)
+  double inv_vdt, t0_over_dt;
+  float inv_vdt_f;
 };
 
 // The taps of one stage of sensors for one lane's kernel.  NT > 0: every
@@ -459,32 +545,48 @@ template <int NT, bool SIG>
 __device__ __forceinline__ void adjoint_stage(const AdjPair &c, int nsb, float &pA, float &pS) {
   const KernelRec &r = *c.r;
   for (int js = 0; js < nsb; ++js) {
-    const double4 s = c.sens[c.j0 + js];
-    const int nb = c.nbs[js];
-    const PairTerms pt = pair_terms(s.x, s.y, s.z, r.cx, r.cy, r.cz, r.h, c.inv_vdt,
-                                    c.t0_over_dt);
-    const float d0 = (float)(pt.fr * c.vdt);
-    const int nvalid = (pt.fr >= r.hlast) ? r.ntap : r.ntap - 1;
-    const int o = min(max(pt.lo - nb, 0), c.omax);
-    const float f = 0.5f * pt.rinv * __builtin_amdgcn_exp2f(r.c * d0 * d0);
-    const float q = __builtin_amdgcn_exp2f(fmaf(r.k1, d0, r.k2));
-    const float *row = c.stage + js * c.L + o;
+    const float4 U = c.su[js];
+    const float4 V = c.sv[js];
+    // One sensor for the whole wave: these are uniform.
+    const int kit = c.kit;
+    const int nb = __builtin_amdgcn_readfirstlane(c.nbs[js]);
+    PairW p;
+    if (kit >= 0) {
+      BlockLane bl;
+      bl.m2ux = U.x;
+      bl.m2uy = U.y;
+      bl.m2uz = U.z;
+      bl.inv2R = U.w;
+      bl.Rf = V.x;
+      bl.Xf = V.y;
+      bl.Xi = __builtin_amdgcn_readfirstlane(__float_as_int(V.z));
+      if (pair_filter(bl, kit, r.dx, r.dy, r.dz, r.dd, r.hf, r.H, c.inv_vdt_f, p))
+        pair_exact<false>(c.sens[c.j0 + js], r.fcx, r.fcy, r.fcz, r.h, r.ntap, nb, c.inv_vdt,
+                          c.t0_over_dt, p);
+    } else {
+      pair_exact<true>(c.sens[c.j0 + js], r.fcx, r.fcy, r.fcz, r.h, r.ntap, nb, c.inv_vdt,
+                       c.t0_over_dt, p);
+    }
+    const float d0 = p.d0;
+    const int nvalid = p.last_ok ? r.ntap : r.ntap - 1;
+    const float f = p.rinv * __builtin_amdgcn_exp2f(r.c * d0 * d0);
+    const float q = __builtin_amdgcn_exp2f(fmaf(r.k1, d0, r.c));
+    const float *row = c.stage + js * c.L + p.o;
     if (NT > 0) {
-      gather_taps<(NT > 0 ? NT : 1), SIG>(row, f, q, d0, r.rq, c.vdt_f, nvalid, pA, pS);
+      gather_taps<(NT > 0 ? NT : 1), SIG>(row, f, q, d0, r.rq, nvalid, pA, pS);
     } else {
       // Any tap count: the Gaussian factors are re-evaluated every kTapRun
       // taps, as in the forward.
-      const float w = 0.5f * pt.rinv;
       for (int i0 = 0; i0 < nvalid; i0 += kTapRun) {
-        float d = fmaf(-(float)i0, c.vdt_f, d0);
-        float ff = w * __builtin_amdgcn_exp2f(r.c * d * d);
-        float qq = __builtin_amdgcn_exp2f(fmaf(r.k1, d, r.k2));
+        float d = d0 - (float)i0;
+        float ff = p.rinv * __builtin_amdgcn_exp2f(r.c * d * d);
+        float qq = __builtin_amdgcn_exp2f(fmaf(r.k1, d, r.c));
         const int iend = min(i0 + kTapRun, nvalid);
         for (int it = i0; it < iend; ++it) {
           const float pd = row[it] * ff * d;
           pA += pd;
           if (SIG) pS = fmaf(pd, d * d, pS);
-          d -= c.vdt_f;
+          d -= 1.0f;
           ff *= qq;
           qq *= r.rq;
         }
@@ -498,7 +600,9 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(const double4 *__restric
                                                        AdjArgs a) {
   extern __shared__ float stage[];  // [kAdjSensorsPerStage][L]
   __shared__ int nbs[kAdjSensorsPerStage];
-  __shared__ int4 tapn[BLOCK / 4];   // tap count of each of the tile's kernels
+  __shared__ float4 su[kAdjSensorsPerStage];
+  __shared__ float4 sv[kAdjSensorsPerStage];
+  __shared__ int4 tapn[BLOCK / 4];  // tap count of each of the tile's kernels
   __shared__ int order[BLOCK];      // tile kernels by tap count
 
   const int64_t logical = xcd_logical_block(a.nlogical);
@@ -545,14 +649,13 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(const double4 *__restric
   c.r = &r;
   c.stage = stage;
   c.nbs = nbs;
+  c.su = su;
+  c.sv = sv;
   c.L = a.L;
-  // By construction every slot a lane reads (its window, plus up to three
-  // padding samples in the unrolled gather) is at most L - 1.
-  c.omax = a.L - (NT > 0 ? NT : r.ntap);
   c.inv_vdt = a.inv_vdt;
   c.t0_over_dt = a.t0_over_dt;
-  c.vdt = a.vdt;
-  c.vdt_f = (float)a.vdt;
+  c.inv_vdt_f = (float)a.inv_vdt;
+  c.kit = T.filter_steps;
 
   double accA = 0.0, accS = 0.0;
   for (int j0 = 0; j0 < a.Nd; j0 += kAdjSensorsPerStage) {
@@ -562,7 +665,12 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(const double4 *__restric
       const double4 s = sens[j0 + t];
       const double dx = s.x - T.cx, dy = s.y - T.cy, dz = s.z - T.cz;
       const double R = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
-      nbs[t] = (int)floor((R - T.rho) * a.inv_vdt - a.t0_over_dt - a.hmax) - 1;
+      const int nb = (int)floor((R - T.rho) * a.inv_vdt - a.t0_over_dt - a.hmax) - 1;
+      nbs[t] = nb;
+      BlockLane bl;
+      block_lane(s, T, nb, a.inv_vdt, a.t0_over_dt, bl);
+      su[t] = make_float4(bl.m2ux, bl.m2uy, bl.m2uz, bl.inv2R);
+      sv[t] = make_float4(bl.Rf, bl.Xf, __int_as_float(bl.Xi), 0.0f);
     }
     __syncthreads();
     // Stage the residual over the tile's time shell: one wave per row, lanes
@@ -594,12 +702,13 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(const double4 *__restric
     if (SIG) accS += (double)pS;
   }
   if (live) {
+    // The sums ran over e/r with offsets in samples: gA = Delta/2 sum delta u e/r,
+    // gsigma = A/2 (Delta/sigma)^3 sum delta u^3 e/r, Delta/sigma = n_sigma/h.
     const int32_t k = a.perm[i];
-    a.gA[k] = (float)accA;
+    a.gA[k] = (float)(accA * 0.5 * a.vdt);
     if (SIG) {
-      // sigma_k (as clamped by the record builder) from h = n_sigma sigma / Delta.
-      const double sg = r.h * a.vdt / a.nsig;
-      a.gS[k] = (float)(accS * (double)r.amp / (sg * sg * sg));
+      const double ds = a.nsig / r.h;
+      a.gS[k] = (float)(accS * 0.5 * (double)r.amp * ds * ds * ds);
     }
   }
 }
@@ -619,7 +728,10 @@ hipError_t launch_forward(const gpair_plan_s *p, float *y, hipStream_t s) {
   FwdArgs a;
   a.sens = (const double4 *)ws_sens(p);
   a.tiles = ws_ftiles(p);
+  a.blocks = ws_atiles(p);
   a.y = y;
+  a.ntiles = (int32_t)p->host.ftiles.size();
+  a.nblocks = (int32_t)p->host.atiles.size();
   a.Nd = p->Nd;
   a.Nt = p->Nt;
   a.nsg = (p->Nd + kWave - 1) / kWave;

@@ -177,19 +177,17 @@ Keys morton_keys(const gpair_geometry *g) {
   return out;
 }
 
-// Cut the Morton-ordered kernels into tiles of at most `tile` members that
-// never cross an aligned Morton block of 8^level cells.
-std::vector<TileInfo> make_tiles(const HostVec<uint64_t> &sorted_keys,
-                                 const HostVec<double> &kgeo, int64_t tile,
-                                 int level) {
-  std::vector<TileInfo> tiles;
-  const int64_t m = (int64_t)sorted_keys.size();
+// Cut the Morton-ordered kernels [s0, e0) into tiles of at most `tile`
+// members that never cross an aligned Morton block of 8^level cells, and
+// append them to `tiles`.
+void cut_tiles(const HostVec<uint64_t> &sorted_keys, const HostVec<double> &kgeo, int64_t tile,
+               int level, int64_t s0, int64_t e0, std::vector<TileInfo> &tiles) {
   const int shift = 3 * level;
-  int64_t s = 0;
-  while (s < m) {
+  int64_t s = s0;
+  while (s < e0) {
     const uint64_t blk = shift >= 64 ? 0 : (sorted_keys[s] >> shift);
     int64_t e = s + 1;
-    while (e < m && e - s < tile &&
+    while (e < e0 && e - s < tile &&
            (shift >= 64 ? 0 : (sorted_keys[e] >> shift)) == blk)
       ++e;
     TileInfo t{};
@@ -211,8 +209,29 @@ std::vector<TileInfo> make_tiles(const HostVec<uint64_t> &sorted_keys,
     t.rho = std::sqrt(r2) * (1.0 + 1e-12) + 1e-15;
     t.start = (int32_t)s;
     t.count = (int32_t)(e - s);
+    t.first_block = -1;
     tiles.push_back(t);
     s = e;
+  }
+}
+
+std::vector<TileInfo> make_tiles(const HostVec<uint64_t> &sorted_keys,
+                                 const HostVec<double> &kgeo, int64_t tile, int level) {
+  std::vector<TileInfo> tiles;
+  cut_tiles(sorted_keys, kgeo, tile, level, 0, (int64_t)sorted_keys.size(), tiles);
+  return tiles;
+}
+
+// Adjoint tiles cut inside each forward tile (so that every forward tile is
+// a whole number of adjoint tiles, its reference blocks); sets each forward
+// tile's first_block.
+std::vector<TileInfo> make_nested_tiles(const HostVec<uint64_t> &sorted_keys,
+                                        const HostVec<double> &kgeo,
+                                        std::vector<TileInfo> &ftiles, int64_t tile, int level) {
+  std::vector<TileInfo> tiles;
+  for (TileInfo &F : ftiles) {
+    F.first_block = (int32_t)tiles.size();
+    cut_tiles(sorted_keys, kgeo, tile, level, F.start, (int64_t)F.start + F.count, tiles);
   }
   return tiles;
 }
@@ -290,6 +309,52 @@ int64_t max_slot(const gpair_plan_s *p, const std::vector<TileInfo> &tiles) {
     w = std::max(w, x);
   }
   return w;
+}
+
+}  // namespace
+
+int filter_steps(double R, double rho, double inv_vdt, double hmax) {
+  if (!(R > 4.0 * rho)) return -1;
+  // |dr| <= rho; the first estimate D/(2R) is off by dr^2/(2R) <= rho^2/(2R)
+  // and each step multiplies the error by at most kappa.
+  const double kappa = (2.0 * rho + rho * rho / (2.0 * R)) / (2.0 * R);
+  double e = rho * rho / (2.0 * R) * inv_vdt;
+  int k = 0;
+  while (e > kFilterIterTol && k < kFilterMaxSteps) {
+    e *= kappa;
+    ++k;
+  }
+  // Rounding: D carries about 5 float32 units of 2R rho (the rounded
+  // coordinates and three fused multiply-adds), the steps and 1/(2R) and
+  // 1/(v dt) about 9 units of rho, so dr is within 14 units of rho; the sum
+  // z = (Xf - h) + dr/(v dt) adds 2 units of its magnitude.
+  const double zmax = 2.0 + hmax + rho * inv_vdt;
+  const double bound = 0x1p-24 * (14.0 * rho * inv_vdt + 2.0 * zmax) + e;
+  if (e > kFilterIterTol || !(bound < 0.5 * kFilterGuard)) return -1;
+  return k;
+}
+
+namespace {
+
+// Filter steps of every adjoint tile: from its closest sensor (the step
+// count grows as R falls), about the float32-rounded centre the operators
+// use as the reference point.
+void set_filter_steps(const gpair_plan_s *p, std::vector<TileInfo> &blocks) {
+  parallel_ranges((int64_t)blocks.size(), [&](int64_t b0, int64_t b1) {
+    for (int64_t b = b0; b < b1; ++b) {
+      TileInfo &B = blocks[b];
+      const double bx = (float)B.cx, by = (float)B.cy, bz = (float)B.cz;
+      double R2 = std::numeric_limits<double>::infinity();
+      for (int32_t j = 0; j < p->Nd; ++j) {
+        const double *s = &p->host.sens[4 * (size_t)j];
+        const double ux = s[0] - bx, uy = s[1] - by, uz = s[2] - bz;
+        R2 = std::min(R2, ux * ux + uy * uy + uz * uz);
+      }
+      const double ex = bx - B.cx, ey = by - B.cy, ez = bz - B.cz;
+      const double rho = B.rho + std::sqrt(ex * ex + ey * ey + ez * ez);
+      B.filter_steps = filter_steps(std::sqrt(R2) * (1.0 - 1e-12), rho, p->inv_vdt, p->hmax);
+    }
+  });
 }
 
 }  // namespace
@@ -456,9 +521,10 @@ gpair_status build_plan(const gpair_geometry *g, gpair_plan_s *p) {
   p->fwd_tile = (int32_t)Tf;
   p->fwd_waves = g->fwd_waves ? g->fwd_waves : 4;
 
-  int64_t Ta = g->adj_tile ? g->adj_tile : 256;
+  // Adjoint tiles nest in forward tiles: at most the forward tile size.
+  int64_t Ta = std::min<int64_t>(g->adj_tile ? g->adj_tile : 256, Tf);
   for (;;) {
-    h.atiles = make_tiles(skeys, h.kgeo, Ta, level_of(Ta));
+    h.atiles = make_nested_tiles(skeys, h.kgeo, h.ftiles, Ta, level_of(Ta));
     p->La = segment_len(max_rho(h.atiles), p->inv_vdt, p->hmax);
     if ((int64_t)p->La * kAdjSensorsPerStage * 4 <= kMaxSegmentBytes || Ta <= 64) break;
     Ta /= 2;
@@ -466,6 +532,7 @@ gpair_status build_plan(const gpair_geometry *g, gpair_plan_s *p) {
   if ((int64_t)p->La * kAdjSensorsPerStage * 4 > kMaxSegmentBytes) return GPAIR_ERR_INVALID_ARG;
   p->adj_tile = (int32_t)Ta;
   p->max_rho = std::max(max_rho(h.ftiles), max_rho(h.atiles));
+  set_filter_steps(p, h.atiles);
 
   // The binning invariant: every slot a pair can touch lies in its segment.
   {

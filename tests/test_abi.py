@@ -7,6 +7,7 @@ import re
 import numpy as np
 import pytest
 
+from paper_2602_03893_amd import inputs as I
 from tests.conftest import ROOT
 
 HEADERS = [os.path.join(ROOT, "include", h)
@@ -170,4 +171,32 @@ def test_binning_invariant_holds_pair_by_pair(case):
         assert 0 <= lo and hi <= seg - 1, (case, which, lo, hi, seg)
     assert _lib.gpair_plan_tiling_slots(h, 2, ctypes.byref(ctypes.c_int64()),
                                         ctypes.byref(ctypes.c_int64())) == -1
+    _lib.gpair_plan_destroy(h)
+
+
+def test_filter_routes_close_blocks_to_float64():
+    """The planner admits a block to the float32 window filter only when its
+    error bound holds for the closest sensor: at the paper-scale shape every
+    block (radius 0.52 mm, closest sensor 21-40 mm away) takes the filter
+    with three or four steps; a
+    cloud whose blocks are a few radii from the sensors is decided in
+    float64 throughout."""
+    from paper_2602_03893_amd import _lib
+    w = I.WORKLOADS["paper"]
+    cen, sen = I.geometry_arrays(w)
+    g, keep = _geometry(cen, sen, nt=w.n_samples, smax=w.smax)
+    st, h = _create(g)
+    assert st == 0
+    n, k = ctypes.c_int64(), ctypes.c_int32()
+    assert _lib.gpair_plan_filter_stats(h, ctypes.byref(n), ctypes.byref(k)) == 0
+    assert n.value == 0 and k.value == 4
+    _lib.gpair_plan_destroy(h)
+    rng = np.random.default_rng(3)
+    cen = rng.uniform(-2e-3, 2e-3, (150, 3)).astype(np.float32)
+    sen = I.fibonacci_hemisphere(40, 6e-3)
+    g, keep = _geometry(cen, sen, nt=512, smax=0.08e-3, fwd_tile=64, adj_tile=64)
+    st, h = _create(g)
+    assert st == 0
+    assert _lib.gpair_plan_filter_stats(h, ctypes.byref(n), ctypes.byref(k)) == 0
+    assert n.value == 3 and k.value == 0   # 150 kernels: three tiles, all in float64
     _lib.gpair_plan_destroy(h)
