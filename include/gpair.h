@@ -242,6 +242,25 @@ gpair_status gpair_adjoint(gpair_plan p, const float *A, const float *sigma,
                            gpair_stream stream);
 
 /*
+ * gpair_adjoint plus the gradient with respect to the kernel centres
+ * (learnable centres, named as future work in the paper's Discussion): the
+ * derivative of Eq. (single_forward) through r = |s_j - c_k| at fixed window
+ * membership,
+ *   gc_k = sum_j (c_k - s_j)/r * sum_{n in W} delta_j[n] A_k e/(2r)
+ *          (1 - d^2/sigma_k^2 - d/r),
+ * the same a.e. derivative as the sigma-gradient.  The plan's geometry (its
+ * tiling and tile spheres) stays that of plan creation: centres that move
+ * are taken up by creating a plan with the new centres.
+ *  A        device float32 [n_kernels] (required).
+ *  gcentres device float32 [n_kernels][3] (x, y, z), overwritten.
+ *  gA, gsigma as gpair_adjoint (gsigma may be NULL).
+ * Sums over sensors are carried in float64.  Errors: INVALID_ARG, HIP.
+ */
+gpair_status gpair_adjoint_centres(gpair_plan p, const float *A, const float *sigma,
+                                   const float *delta, float *gA, float *gsigma,
+                                   float *gcentres, gpair_stream stream);
+
+/*
  * Synchronise `stream` and return in *count how many sigma_k values outside
  * (0, sigma_max] the operators have met since the plan was created (each
  * forward/adjoint call adds its count).  Errors: INVALID_ARG, HIP.

@@ -109,6 +109,8 @@ gpair_plan_filter_stats = _proto("gpair_plan_filter_stats", c_i32,
                                  [c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i32)])
 gpair_forward = _proto("gpair_forward", c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp])
 gpair_adjoint = _proto("gpair_adjoint", c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp])
+gpair_adjoint_centres = _proto("gpair_adjoint_centres", c_i32,
+                               [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp])
 gpair_sigma_violations = _proto("gpair_sigma_violations", c_i32,
                                 [c_vp, ctypes.POINTER(c_i64), c_vp])
 gpair_residual = _proto("gpair_residual", c_i32, [c_vp, c_vp, c_vp, c_flt, c_vp, c_vp, c_vp])

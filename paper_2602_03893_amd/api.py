@@ -142,6 +142,22 @@ class Plan:
         check(_lib.gpair_adjoint(self._h, pa, ps, pd, pga, pgs, _stream()), "gpair_adjoint")
         return gA, gS
 
+    def adjoint_centres(self, A, sigma, delta, want_sigma=True):
+        """(gA, gsigma or None, gcentres (M, 3)) float32: the adjoint with the
+        gradient with respect to the kernel centres (gpair_adjoint_centres)."""
+        M = self.n_kernels
+        pa = _dev(A, "A", M, device=self.device)
+        ps = _dev(sigma, "sigma", M, device=self.device)
+        pd = _dev(delta, "delta", self.n_sensors * self.n_samples, device=self.device)
+        gA = torch.empty(M, dtype=torch.float32, device=self.device)
+        gS = torch.empty(M, dtype=torch.float32, device=self.device) if want_sigma else None
+        gC = torch.empty((M, 3), dtype=torch.float32, device=self.device)
+        check(_lib.gpair_adjoint_centres(self._h, pa, ps, pd, _dev(gA, "gA", M),
+                                         _dev(gS, "gsigma", M) if want_sigma else None,
+                                         _dev(gC, "gcentres", 3 * M), _stream()),
+              "gpair_adjoint_centres")
+        return gA, gS, gC
+
     def residual(self, y, b, scale=1.0, delta=None):
         """norms (2,) float64 on device = (sum (y-b)^2, sum b^2); writes
         delta = scale (y - b) when `delta` is given (may be y itself)."""

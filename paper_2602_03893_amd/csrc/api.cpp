@@ -207,7 +207,20 @@ gpair_status gpair_adjoint(gpair_plan p, const float *A, const float *sigma,
   hipError_t e = launch_prep(p, A, sigma, s);
   if (e != hipSuccess) return GPAIR_ERR_HIP;
   timer_begin(p, GPAIR_TIMER_ADJOINT, s);
-  e = launch_adjoint(p, delta, gA, gsigma, s);
+  e = launch_adjoint(p, delta, gA, gsigma, nullptr, s);
+  timer_end(p, GPAIR_TIMER_ADJOINT, s);
+  return hip_status(e);
+}
+
+gpair_status gpair_adjoint_centres(gpair_plan p, const float *A, const float *sigma,
+                                   const float *delta, float *gA, float *gsigma,
+                                   float *gcentres, gpair_stream stream) {
+  if (!bound(p) || !A || !sigma || !delta || !gA || !gcentres) return GPAIR_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_prep(p, A, sigma, s);
+  if (e != hipSuccess) return GPAIR_ERR_HIP;
+  timer_begin(p, GPAIR_TIMER_ADJOINT, s);
+  e = launch_adjoint(p, delta, gA, gsigma, gcentres, s);
   timer_end(p, GPAIR_TIMER_ADJOINT, s);
   return hip_status(e);
 }

@@ -194,8 +194,9 @@ hipError_t launch_scale(float *x, int64_t n, float alpha, hipStream_t s);
 hipError_t launch_dot3(const gpair_plan_s *p, const float *y, const float *b, double *out,
                        hipStream_t s);
 hipError_t launch_forward(const gpair_plan_s *p, float *y, hipStream_t s);
+// gsigma and gcentres may be null (not computed / not written).
 hipError_t launch_adjoint(const gpair_plan_s *p, const float *delta, float *gA,
-                          float *gsigma, hipStream_t s);
+                          float *gsigma, float *gcentres, hipStream_t s);
 hipError_t launch_residual(const gpair_plan_s *p, const float *y, const float *b,
                            float scale, float *delta, double *norms,
                            hipStream_t s);

@@ -491,7 +491,8 @@ struct AdjArgs {
   const int32_t *perm;
   const float *delta;
   float *gA;
-  float *gS;
+  float *gS;   // null: not written
+  float *gC;   // [M][3] centre gradient (MODE 2), caller order
   int64_t nlogical;
   int32_t Nd, Nt, L, ntap_max;
   int32_t rank;  // order the tile's kernels by tap count
@@ -502,13 +503,19 @@ struct AdjArgs {
 // +13% adjoint time at 64 sensors, -2% at 1024 with sigma spread by 5%).
 constexpr int kAdjRankMinSensors = 256;
 
+// What the adjoint accumulates: MODE 0 the amplitude gradient; 1 also the
+// sigma-gradient; 2 also the centre gradient.
+constexpr int kAdjA = 0, kAdjSigma = 1, kAdjCentres = 2;
+
 // Gather the taps of one kernel-sensor pair from a staged residual row (row
 // points at the pair's first sample): NT samples of which the first nvalid
 // are in the window (only the last three can be outside).  All reads are
-// issued first.
-template <int NT, bool SIG>
+// issued first.  With t = delta f (f = e/r) and offsets u in samples:
+// s1 += t u, and for MODE >= 1 s3 += t u^3, for MODE 2 s0 += t, s2 += t u^2.
+template <int NT, int MODE>
 __device__ __forceinline__ void gather_taps(const float *row, float f, float q, float d,
-                                            float rq, int nvalid, float &pA, float &pS) {
+                                            float rq, int nvalid, float &s0, float &s1,
+                                            float &s2, float &s3) {
   float dl[NT];
 #pragma unroll
   for (int i = 0; i < NT; ++i) dl[i] = row[i];
@@ -517,14 +524,32 @@ __device__ __forceinline__ void gather_taps(const float *row, float f, float q, 
     if (i >= nvalid) dl[i] = 0.0f;
 #pragma unroll
   for (int i = 0; i < NT; ++i) {
-    const float pd = dl[i] * f * d;
-    pA += pd;
-    if (SIG) pS = fmaf(pd, d * d, pS);
+    if (MODE == kAdjCentres) {
+      const float t = dl[i] * f;
+      const float d2 = d * d;
+      s0 += t;
+      s2 = fmaf(t, d2, s2);
+      const float pd = t * d;
+      s1 += pd;
+      s3 = fmaf(pd, d2, s3);
+    } else {
+      const float pd = dl[i] * f * d;
+      s1 += pd;
+      if (MODE >= kAdjSigma) s3 = fmaf(pd, d * d, s3);
+    }
     d -= 1.0f;
     f *= q;
     q *= rq;
   }
 }
+
+// Per-lane sums of one stage (float32).
+struct AdjSums {
+  float a;           // sum delta u e/r                          (amplitude)
+  float s;           // sum delta u^3 e/r                        (sigma)
+  float cx, cy, cz;  // sum over pairs of (c - s)/r G, G = sum delta e/r
+                     //   (1 - u^2/sigma_u^2) - (Delta/r) sum delta u e/r   (centres)
+};
 
 struct AdjPair {
   const double4 *sens;
@@ -537,12 +562,15 @@ struct AdjPair {
   int kit;           // the tile's filter steps, or -1 (every pair in float64)
   double inv_vdt, t0_over_dt;
   float inv_vdt_f;
+  float vdt_f;       // Delta (m)
 };
 
 // The taps of one stage of sensors for one lane's kernel.  NT > 0: every
 // kernel of the wave has NT - 2 .. NT taps (fully unrolled); NT = 0: any.
-template <int NT, bool SIG>
-__device__ __forceinline__ void adjoint_stage(const AdjPair &c, int nsb, float &pA, float &pS) {
+// isg2 = (Delta/sigma_k)^2 (MODE 2).
+template <int NT, int MODE>
+__device__ __forceinline__ void adjoint_stage(const AdjPair &c, int nsb, float isg2,
+                                              AdjSums &acc) {
   const KernelRec &r = *c.r;
   for (int js = 0; js < nsb; ++js) {
     const float4 U = c.su[js];
@@ -572,8 +600,13 @@ __device__ __forceinline__ void adjoint_stage(const AdjPair &c, int nsb, float &
     const float f = p.rinv * __builtin_amdgcn_exp2f(r.c * d0 * d0);
     const float q = __builtin_amdgcn_exp2f(fmaf(r.k1, d0, r.c));
     const float *row = c.stage + js * c.L + p.o;
+    // MODE 2 needs the pair's own sums; otherwise taps add straight into the
+    // stage's sums.
+    float t0 = 0.0f, t1 = 0.0f, t2 = 0.0f, t3 = 0.0f;
+    float &s1 = MODE == kAdjCentres ? t1 : acc.a;
+    float &s3 = MODE == kAdjCentres ? t3 : acc.s;
     if (NT > 0) {
-      gather_taps<(NT > 0 ? NT : 1), SIG>(row, f, q, d0, r.rq, nvalid, pA, pS);
+      gather_taps<(NT > 0 ? NT : 1), MODE>(row, f, q, d0, r.rq, nvalid, t0, s1, t2, s3);
     } else {
       // Any tap count: the Gaussian factors are re-evaluated every kTapRun
       // taps, as in the forward.
@@ -583,19 +616,34 @@ __device__ __forceinline__ void adjoint_stage(const AdjPair &c, int nsb, float &
         float qq = __builtin_amdgcn_exp2f(fmaf(r.k1, d, r.c));
         const int iend = min(i0 + kTapRun, nvalid);
         for (int it = i0; it < iend; ++it) {
-          const float pd = row[it] * ff * d;
-          pA += pd;
-          if (SIG) pS = fmaf(pd, d * d, pS);
+          const float t = row[it] * ff;
+          const float pd = t * d;
+          s1 += pd;
+          if (MODE >= kAdjSigma) s3 = fmaf(pd, d * d, s3);
+          if (MODE == kAdjCentres) {
+            t0 += t;
+            t2 = fmaf(t, d * d, t2);
+          }
           d -= 1.0f;
           ff *= qq;
           qq *= r.rq;
         }
       }
     }
+    if (MODE == kAdjCentres) {
+      acc.a += t1;
+      acc.s += t3;
+      // c - s = dk + (-2u)/2; G/r along (c - s)/r.
+      const float g = fmaf(-t2, isg2, t0) - (c.vdt_f * p.rinv) * t1;
+      const float w = g * p.rinv;
+      acc.cx = fmaf(w, fmaf(U.x, 0.5f, r.dx), acc.cx);
+      acc.cy = fmaf(w, fmaf(U.y, 0.5f, r.dy), acc.cy);
+      acc.cz = fmaf(w, fmaf(U.z, 0.5f, r.dz), acc.cz);
+    }
   }
 }
 
-template <int BLOCK, bool SIG>
+template <int BLOCK, int MODE>
 __global__ __launch_bounds__(BLOCK) void adjoint_kernel(const double4 *__restrict__ sens,
                                                        AdjArgs a) {
   extern __shared__ float stage[];  // [kAdjSensorsPerStage][L]
@@ -655,9 +703,15 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(const double4 *__restric
   c.inv_vdt = a.inv_vdt;
   c.t0_over_dt = a.t0_over_dt;
   c.inv_vdt_f = (float)a.inv_vdt;
+  c.vdt_f = (float)a.vdt;
   c.kit = T.filter_steps;
 
-  double accA = 0.0, accS = 0.0;
+  float isg2 = 0.0f;
+  if (MODE == kAdjCentres) {
+    const double ds = a.nsig / r.h;  // Delta / sigma_k
+    isg2 = (float)(ds * ds);
+  }
+  double accA = 0.0, accS = 0.0, accC[3] = {0.0, 0.0, 0.0};
   for (int j0 = 0; j0 < a.Nd; j0 += kAdjSensorsPerStage) {
     const int nsb = min(kAdjSensorsPerStage, a.Nd - j0);
     __syncthreads();  // the previous stage has been consumed
@@ -686,29 +740,41 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(const double4 *__restric
     __syncthreads();
 
     c.j0 = j0;
-    float pA = 0.0f, pS = 0.0f;
+    AdjSums sums = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     switch (NT) {
 #define GPAIR_ADJ_CASE(n) \
-  case n: adjoint_stage<n, SIG>(c, nsb, pA, pS); break;
+  case n: adjoint_stage<n, MODE>(c, nsb, isg2, sums); break;
       GPAIR_ADJ_CASE(2) GPAIR_ADJ_CASE(3) GPAIR_ADJ_CASE(4) GPAIR_ADJ_CASE(5)
       GPAIR_ADJ_CASE(6) GPAIR_ADJ_CASE(7) GPAIR_ADJ_CASE(8) GPAIR_ADJ_CASE(9)
       GPAIR_ADJ_CASE(10) GPAIR_ADJ_CASE(11) GPAIR_ADJ_CASE(12) GPAIR_ADJ_CASE(13)
       GPAIR_ADJ_CASE(14) GPAIR_ADJ_CASE(15) GPAIR_ADJ_CASE(16) GPAIR_ADJ_CASE(17)
       GPAIR_ADJ_CASE(18)
-      default: adjoint_stage<0, SIG>(c, nsb, pA, pS); break;
+      default: adjoint_stage<0, MODE>(c, nsb, isg2, sums); break;
 #undef GPAIR_ADJ_CASE
     }
-    accA += (double)pA;
-    if (SIG) accS += (double)pS;
+    accA += (double)sums.a;
+    if (MODE >= kAdjSigma) accS += (double)sums.s;
+    if (MODE == kAdjCentres) {
+      accC[0] += (double)sums.cx;
+      accC[1] += (double)sums.cy;
+      accC[2] += (double)sums.cz;
+    }
   }
   if (live) {
     // The sums ran over e/r with offsets in samples: gA = Delta/2 sum delta u e/r,
     // gsigma = A/2 (Delta/sigma)^3 sum delta u^3 e/r, Delta/sigma = n_sigma/h.
+    // gc = A/2 sum over pairs of (c - s)/r G.
     const int32_t k = a.perm[i];
     a.gA[k] = (float)(accA * 0.5 * a.vdt);
-    if (SIG) {
+    if (MODE >= kAdjSigma && a.gS) {
       const double ds = a.nsig / r.h;
       a.gS[k] = (float)(accS * 0.5 * (double)r.amp * ds * ds * ds);
+    }
+    if (MODE == kAdjCentres) {
+      const double h = 0.5 * (double)r.amp;
+      a.gC[3 * (int64_t)k] = (float)(accC[0] * h);
+      a.gC[3 * (int64_t)k + 1] = (float)(accC[1] * h);
+      a.gC[3 * (int64_t)k + 2] = (float)(accC[2] * h);
     }
   }
 }
@@ -758,7 +824,7 @@ hipError_t launch_forward(const gpair_plan_s *p, float *y, hipStream_t s) {
 }
 
 hipError_t launch_adjoint(const gpair_plan_s *p, const float *delta, float *gA,
-                          float *gsigma, hipStream_t s) {
+                          float *gsigma, float *gcentres, hipStream_t s) {
   AdjArgs a;
   a.krec = ws_krec(p);
   a.tiles = ws_atiles(p);
@@ -766,6 +832,7 @@ hipError_t launch_adjoint(const gpair_plan_s *p, const float *delta, float *gA,
   a.delta = delta;
   a.gA = gA;
   a.gS = gsigma;
+  a.gC = gcentres;
   a.nlogical = (int64_t)p->host.atiles.size();
   a.Nd = p->Nd;
   a.Nt = p->Nt;
@@ -779,21 +846,20 @@ hipError_t launch_adjoint(const gpair_plan_s *p, const float *delta, float *gA,
   a.rank = p->Nd >= kAdjRankMinSensors ? 1 : 0;
   const size_t lds = (size_t)p->La * kAdjSensorsPerStage * sizeof(float);
   const unsigned int grid = xcd_grid(a.nlogical);
-  const bool sig = gsigma != nullptr;
-  switch (p->adj_tile) {
-    case 64:
-      if (sig) adjoint_kernel<64, true><<<grid, 64, lds, s>>>((const double4 *)ws_sens(p), a);
-      else adjoint_kernel<64, false><<<grid, 64, lds, s>>>((const double4 *)ws_sens(p), a);
-      break;
-    case 128:
-      if (sig) adjoint_kernel<128, true><<<grid, 128, lds, s>>>((const double4 *)ws_sens(p), a);
-      else adjoint_kernel<128, false><<<grid, 128, lds, s>>>((const double4 *)ws_sens(p), a);
-      break;
-    default:
-      if (sig) adjoint_kernel<256, true><<<grid, 256, lds, s>>>((const double4 *)ws_sens(p), a);
-      else adjoint_kernel<256, false><<<grid, 256, lds, s>>>((const double4 *)ws_sens(p), a);
-      break;
+  const double4 *sens = (const double4 *)ws_sens(p);
+  const int mode = gcentres ? kAdjCentres : (gsigma ? kAdjSigma : kAdjA);
+#define GPAIR_ADJ_LAUNCH(B)                                                          \
+  switch (mode) {                                                                    \
+    case kAdjA: adjoint_kernel<B, kAdjA><<<grid, B, lds, s>>>(sens, a); break;        \
+    case kAdjSigma: adjoint_kernel<B, kAdjSigma><<<grid, B, lds, s>>>(sens, a); break; \
+    default: adjoint_kernel<B, kAdjCentres><<<grid, B, lds, s>>>(sens, a); break;     \
   }
+  switch (p->adj_tile) {
+    case 64: GPAIR_ADJ_LAUNCH(64) break;
+    case 128: GPAIR_ADJ_LAUNCH(128) break;
+    default: GPAIR_ADJ_LAUNCH(256) break;
+  }
+#undef GPAIR_ADJ_LAUNCH
   return hipGetLastError();
 }
 
