@@ -579,9 +579,10 @@ def main():
         state["t"] += 1
         if obj:
             obj.x_from_z(A)
-        plan.forward(A, sigma, out=y)
+        plan.prepare(A, sigma)           # records once for both operators
+        plan.forward_prepared(out=y)
         plan.residual(y, b, scale=scale, delta=y)
-        plan.adjoint(A, sigma, y, want_sigma=True, out_A=gA, out_sigma=gS)
+        plan.adjoint_prepared(y, want_sigma=True, out_A=gA, out_sigma=gS)
         if obj:
             obj.add_reg_and_chain(A, gA)
             adam_update(obj.z, gA, mA, vA, state["t"], obj.lr(state["t"], lr_A))

@@ -108,6 +108,7 @@ typedef struct gpair_geometry {
   int32_t fwd_tile;
   int32_t adj_tile;
   int32_t fwd_waves;
+  int32_t deterministic;  /* != 0: bitwise reproducible forward (see gpair_forward) */
 } gpair_geometry;
 
 typedef struct gpair_plan_s *gpair_plan;
@@ -200,11 +201,16 @@ gpair_status gpair_plan_filter_stats(gpair_plan p, int64_t *float64_blocks, int3
  *            * exp(-d^2 / (2 sigma_k^2)),   d = r_jk - v (t0 + n dt),
  * i.e. Eq. (single_forward) summed over the kernels by linearity of the wave
  * equation, with the window of the "3 sigma principle" (inclusive) and
- * samples outside [0, n_samples) dropped.  r_jk = |s_j - c_k| and the window
- * membership are decided in float64; taps are evaluated in float32.  The
+ * samples outside [0, n_samples) dropped.  Window membership is the float64
+ * decision (a float32 filter with a guard, and float64 for the pairs within
+ * the guard of a window edge); taps are evaluated in float32.  The
  * partial sum of each group of nearby kernels (a tile) at a sensor is carried
  * in 32-bit fixed point whose unit is 2^-30 of a bound on that sum
- * (sum_k |A_k| sigma_max e^{-1/2} / (2 r_min)), then added to y in float32.
+ * (sum_k |A_k| sigma_max e^{-1/2} / (2 r_min)), then added to y in float32
+ * (float atomics: the last bits of y depend on the order of the tiles).  With
+ * the plan's `deterministic` set, each tile sum is instead rounded to a
+ * global 64-bit fixed-point unit (2^-62 of a bound on every sample) and added
+ * with integer atomics, so y is bitwise reproducible run to run.
  *  A      device float32 [n_kernels]  amplitudes A_k (any sign).
  *  sigma  device float32 [n_kernels]  widths sigma_k in (0, sigma_max].
  *  y      device float32 [n_sensors][n_samples], overwritten.
@@ -259,6 +265,24 @@ gpair_status gpair_adjoint(gpair_plan p, const float *A, const float *sigma,
 gpair_status gpair_adjoint_centres(gpair_plan p, const float *A, const float *sigma,
                                    const float *delta, float *gA, float *gsigma,
                                    float *gcentres, gpair_stream stream);
+
+/*
+ * The same operators in two steps, for callers that apply the forward and
+ * the adjoint to the same (A, sigma), as one iteration of Algorithm 2 does:
+ * gpair_prepare builds the per-kernel coefficients from (A, sigma) (A may be
+ * NULL: zero amplitudes), and the _prepared calls use the coefficients of the
+ * last direct-operator call that built them on this plan (gpair_prepare,
+ * gpair_forward, gpair_adjoint, gpair_adjoint_centres).  A gsigma request
+ * needs coefficients built with A.  An ASSA call on the plan overwrites the
+ * coefficients: a _prepared call after it, or before any build, returns
+ * INVALID_ARG.  Same results, bit for bit, as gpair_forward / gpair_adjoint.
+ * Errors: INVALID_ARG, HIP.
+ */
+gpair_status gpair_prepare(gpair_plan p, const float *A, const float *sigma,
+                           gpair_stream stream);
+gpair_status gpair_forward_prepared(gpair_plan p, float *y, gpair_stream stream);
+gpair_status gpair_adjoint_prepared(gpair_plan p, const float *delta, float *gA,
+                                    float *gsigma, gpair_stream stream);
 
 /*
  * Synchronise `stream` and return in *count how many sigma_k values outside

@@ -268,55 +268,75 @@ def unet_forward(levels, params, x, round_bf16=True):
     return y, acts
 
 
-def unet_backward(levels, params, x, gy, round_bf16=True):
+def unet_backward(levels, params, x, gy, round_bf16=True, magnitudes=False):
     """Gradient of sum(gy * y) with respect to the flat parameter vector,
     by the chain rule through the layers of ``unet_forward`` in reverse order.
     With round_bf16 every activation gradient is rounded to bfloat16 where the
-    GPU path stores it (weight and bias gradients stay exact)."""
+    GPU path stores it (weight and bias gradients stay exact).  magnitudes:
+    also return, per parameter, the sum of the absolute values of the terms
+    its gradient adds up (the same sums on |activation| and |gradient|)."""
     r = bf16 if round_bf16 else (lambda a: np.asarray(a, np.float64))
     p, n_par = unpack_params(levels, params)
     _, A = unet_forward(levels, params, x, round_bf16)
     grads = {}
+    mags = {}
+    ab = np.abs
+
+    def wg3(name, a, g):
+        grads[name] = conv3_wgrad(a, g)
+        if magnitudes:
+            mags[name] = conv3_wgrad(ab(a), ab(g))
+
+    def wgu(name, a, g):
+        grads[name] = upconv2_wgrad(a, g)
+        if magnitudes:
+            mags[name] = upconv2_wgrad(ab(a), ab(g))
     hlast = A["db0"] if levels >= 2 else A["botb"]
     w, _ = p["head"]
     gin, dw, db = head_backward(hlast, w, A["y"], gy)
     grads["head"] = (dw, np.array([db]))
+    if magnitudes:
+        _, mw, mb = head_backward(ab(hlast), w, A["y"], ab(gy))
+        mags["head"] = (mw, np.array([mb]))
     g = r(gin)
     skip = {}
     for l in range(levels - 1):
         C = 16 * 2 ** l
-        grads[f"dec{l}b"] = conv3_wgrad(A[f"da{l}"], g)
+        wg3(f"dec{l}b", A[f"da{l}"], g)
         g_da = r(conv3_dgrad(g, r(p[f"dec{l}b"][0]), mask_act=A[f"da{l}"]))
-        grads[f"dec{l}a"] = conv3_wgrad(A[f"cat{l}"], g_da)
+        wg3(f"dec{l}a", A[f"cat{l}"], g_da)
         g_cat = r(conv3_dgrad(g_da, r(p[f"dec{l}a"][0])))
         skip[l] = g_cat[..., C:]
         hin = A[f"db{l + 1}"] if l + 1 <= levels - 2 else A["botb"]
-        grads[f"up{l}"] = upconv2_wgrad(hin, g_cat[..., :C])
+        wgu(f"up{l}", hin, g_cat[..., :C])
         g = r(upconv2_dgrad(g_cat[..., :C], r(p[f"up{l}"][0]), mask_act=hin))
-    grads["bot_b"] = conv3_wgrad(A["bota"], g)
+    wg3("bot_b", A["bota"], g)
     g_ba = r(conv3_dgrad(g, r(p["bot_b"][0]), mask_act=A["bota"]))
     in_b = A[f"p{levels - 2}"] if levels >= 2 else A["in"]
-    grads["bot_a"] = conv3_wgrad(in_b, g_ba)
+    wg3("bot_a", in_b, g_ba)
     if levels >= 2:
         g_p = r(conv3_dgrad(g_ba, r(p["bot_a"][0])))
     for l in range(levels - 2, -1, -1):
         g_e = r(maxpool2_backward(g_p, A[f"arg{l}"], A[f"e{l}"], gskip=skip[l]))
-        grads[f"enc{l}b"] = conv3_wgrad(A[f"a{l}"], g_e)
+        wg3(f"enc{l}b", A[f"a{l}"], g_e)
         g_a = r(conv3_dgrad(g_e, r(p[f"enc{l}b"][0]), mask_act=A[f"a{l}"]))
         in_l = A["in"] if l == 0 else A[f"p{l - 1}"]
-        grads[f"enc{l}a"] = conv3_wgrad(in_l, g_a)
+        wg3(f"enc{l}a", in_l, g_a)
         if l > 0:
             g_p = r(conv3_dgrad(g_a, r(p[f"enc{l}a"][0])))
-    flat = np.empty(n_par)
-    off = 0
-    for name, kind, taps, ci, co in unet_layers(levels):
-        dw, db = grads[name]
-        nw = taps * ci * co
-        flat[off:off + nw] = np.asarray(dw).reshape(-1)
-        off += nw
-        flat[off:off + co] = np.asarray(db).reshape(-1)
-        off += co
-    return flat
+
+    def flatten(d):
+        flat = np.empty(n_par)
+        off = 0
+        for name, kind, taps, ci, co in unet_layers(levels):
+            dw, db = d[name]
+            nw = taps * ci * co
+            flat[off:off + nw] = np.asarray(dw).reshape(-1)
+            off += nw
+            flat[off:off + co] = np.asarray(db).reshape(-1)
+            off += co
+        return flat
+    return (flatten(grads), flatten(mags)) if magnitudes else flatten(grads)
 
 
 def unet_loss_and_grad(levels, params, x, target):

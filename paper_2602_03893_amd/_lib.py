@@ -54,7 +54,7 @@ class Geometry(ctypes.Structure):
                 ("n_sensors", c_i32), ("sensors", c_fp), ("n_samples", c_i32),
                 ("dt", c_dbl), ("t0", c_dbl), ("c_sound", c_dbl), ("n_sigma", c_dbl),
                 ("sigma_max", c_dbl), ("fwd_tile", c_i32), ("adj_tile", c_i32),
-                ("fwd_waves", c_i32)]
+                ("fwd_waves", c_i32), ("deterministic", c_i32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -108,6 +108,9 @@ gpair_plan_tiling_slots = _proto("gpair_plan_tiling_slots", c_i32,
 gpair_plan_filter_stats = _proto("gpair_plan_filter_stats", c_i32,
                                  [c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i32)])
 gpair_forward = _proto("gpair_forward", c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp])
+gpair_prepare = _proto("gpair_prepare", c_i32, [c_vp, c_vp, c_vp, c_vp])
+gpair_forward_prepared = _proto("gpair_forward_prepared", c_i32, [c_vp, c_vp, c_vp])
+gpair_adjoint_prepared = _proto("gpair_adjoint_prepared", c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp])
 gpair_adjoint = _proto("gpair_adjoint", c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp])
 gpair_adjoint_centres = _proto("gpair_adjoint_centres", c_i32,
                                [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp])

@@ -40,11 +40,12 @@ class Plan:
     centres  (M, 3) kernel centres in metres (host array-like, taken as float32)
     sensors  (N_d, 3) sensor positions in metres
     n_samples, dt, t0, c_sound, n_sigma, sigma_max: see gpair_geometry.
+    deterministic: bitwise reproducible forward (int64 flush; gpair_forward).
     """
 
     def __init__(self, centres, sensors, n_samples, dt, c_sound, n_sigma=3.0,
                  sigma_max=None, t0=0.0, fwd_tile=0, adj_tile=0, fwd_waves=0,
-                 device=None):
+                 device=None, deterministic=False):
         if sigma_max is None:
             raise ValueError("sigma_max is required")
         c = np.ascontiguousarray(np.asarray(centres, dtype=np.float32).reshape(-1, 3))
@@ -69,6 +70,7 @@ class Plan:
         g.fwd_tile = int(fwd_tile)
         g.adj_tile = int(adj_tile)
         g.fwd_waves = int(fwd_waves)
+        g.deterministic = 1 if deterministic else 0
         self.device = torch.device(device) if device is not None else torch.device(
             "cuda", torch.cuda.current_device())
         self._h = ctypes.c_void_p()
@@ -140,6 +142,38 @@ class Plan:
                                                                      device=self.device)
             pgs = _dev(gS, "gsigma", M, device=self.device)
         check(_lib.gpair_adjoint(self._h, pa, ps, pd, pga, pgs, _stream()), "gpair_adjoint")
+        return gA, gS
+
+    def prepare(self, A, sigma):
+        """Build the coefficient records from (A, sigma) for the _prepared
+        calls (gpair_prepare); A may be None (zero amplitudes)."""
+        M = self.n_kernels
+        pa = _dev(A, "A", M, device=self.device) if A is not None else None
+        check(_lib.gpair_prepare(self._h, pa, _dev(sigma, "sigma", M, device=self.device),
+                                 _stream()), "gpair_prepare")
+
+    def forward_prepared(self, out=None):
+        """y = A(x; sigma) with the records of the last build."""
+        if out is None:
+            out = torch.empty((self.n_sensors, self.n_samples), dtype=torch.float32,
+                              device=self.device)
+        py = _dev(out, "y", self.n_sensors * self.n_samples, device=self.device)
+        check(_lib.gpair_forward_prepared(self._h, py, _stream()), "gpair_forward_prepared")
+        return out
+
+    def adjoint_prepared(self, delta, want_sigma=True, out_A=None, out_sigma=None):
+        """(gA, gsigma or None) with the records of the last build."""
+        M = self.n_kernels
+        pd = _dev(delta, "delta", self.n_sensors * self.n_samples, device=self.device)
+        gA = out_A if out_A is not None else torch.empty(M, dtype=torch.float32, device=self.device)
+        gS = None
+        if want_sigma:
+            gS = out_sigma if out_sigma is not None else torch.empty(M, dtype=torch.float32,
+                                                                     device=self.device)
+        check(_lib.gpair_adjoint_prepared(self._h, pd, _dev(gA, "gA", M, device=self.device),
+                                          _dev(gS, "gsigma", M, device=self.device)
+                                          if want_sigma else None, _stream()),
+              "gpair_adjoint_prepared")
         return gA, gS
 
     def adjoint_centres(self, A, sigma, delta, want_sigma=True):

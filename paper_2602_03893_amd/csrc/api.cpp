@@ -46,6 +46,7 @@ gpair_status gpair_plan_create(const gpair_geometry *g, gpair_plan *out) {
     p->ws = nullptr;
     p->ws_bytes = 0;
     p->timing = 0;
+    p->prepared = 0;
     for (int w = 0; w < GPAIR_TIMER_KINDS; ++w) {
       p->ev_head[w] = p->ev_count[w] = 0;
       for (int i = 0; i < GPAIR_TIMER_SLOTS; ++i) p->ev_start[w][i] = p->ev_stop[w][i] = nullptr;
@@ -185,17 +186,52 @@ static void timer_end(gpair_plan p, int which, hipStream_t s) {
   if (p->ev_count[which] < GPAIR_TIMER_SLOTS) ++p->ev_count[which];
 }
 
-gpair_status gpair_forward(gpair_plan p, const float *A, const float *sigma, float *y,
-                           gpair_stream stream) {
-  if (!bound(p) || !A || !sigma || !y) return GPAIR_ERR_INVALID_ARG;
-  hipStream_t s = (hipStream_t)stream;
-  hipError_t e = launch_prep(p, A, sigma, s);
-  if (e == hipSuccess) e = launch_fill(y, (int64_t)p->Nd * p->Nt, 0.0f, s);
+static hipError_t prep_direct(gpair_plan p, const float *A, const float *sigma, hipStream_t s) {
+  const hipError_t e = launch_prep(p, A, sigma, s);
+  p->prepared = e == hipSuccess ? 1 : 0;
+  return e;
+}
+
+static gpair_status forward_records(gpair_plan p, float *y, hipStream_t s) {
+  hipError_t e = launch_fill(y, (int64_t)p->Nd * p->Nt, 0.0f, s);
   if (e != hipSuccess) return GPAIR_ERR_HIP;
   timer_begin(p, GPAIR_TIMER_FORWARD, s);
   e = launch_forward(p, y, s);
   timer_end(p, GPAIR_TIMER_FORWARD, s);
   return hip_status(e);
+}
+
+static gpair_status adjoint_records(gpair_plan p, const float *delta, float *gA, float *gsigma,
+                                    float *gcentres, hipStream_t s) {
+  timer_begin(p, GPAIR_TIMER_ADJOINT, s);
+  const hipError_t e = launch_adjoint(p, delta, gA, gsigma, gcentres, s);
+  timer_end(p, GPAIR_TIMER_ADJOINT, s);
+  return hip_status(e);
+}
+
+gpair_status gpair_forward(gpair_plan p, const float *A, const float *sigma, float *y,
+                           gpair_stream stream) {
+  if (!bound(p) || !A || !sigma || !y) return GPAIR_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if (prep_direct(p, A, sigma, s) != hipSuccess) return GPAIR_ERR_HIP;
+  return forward_records(p, y, s);
+}
+
+gpair_status gpair_prepare(gpair_plan p, const float *A, const float *sigma,
+                           gpair_stream stream) {
+  if (!bound(p) || !sigma) return GPAIR_ERR_INVALID_ARG;
+  return hip_status(prep_direct(p, A, sigma, (hipStream_t)stream));
+}
+
+gpair_status gpair_forward_prepared(gpair_plan p, float *y, gpair_stream stream) {
+  if (!bound(p) || !y || !p->prepared) return GPAIR_ERR_INVALID_ARG;
+  return forward_records(p, y, (hipStream_t)stream);
+}
+
+gpair_status gpair_adjoint_prepared(gpair_plan p, const float *delta, float *gA, float *gsigma,
+                                    gpair_stream stream) {
+  if (!bound(p) || !delta || !gA || !p->prepared) return GPAIR_ERR_INVALID_ARG;
+  return adjoint_records(p, delta, gA, gsigma, nullptr, (hipStream_t)stream);
 }
 
 gpair_status gpair_adjoint(gpair_plan p, const float *A, const float *sigma,
@@ -204,12 +240,8 @@ gpair_status gpair_adjoint(gpair_plan p, const float *A, const float *sigma,
   if (!bound(p) || !sigma || !delta || !gA) return GPAIR_ERR_INVALID_ARG;
   if (gsigma && !A) return GPAIR_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = launch_prep(p, A, sigma, s);
-  if (e != hipSuccess) return GPAIR_ERR_HIP;
-  timer_begin(p, GPAIR_TIMER_ADJOINT, s);
-  e = launch_adjoint(p, delta, gA, gsigma, nullptr, s);
-  timer_end(p, GPAIR_TIMER_ADJOINT, s);
-  return hip_status(e);
+  if (prep_direct(p, A, sigma, s) != hipSuccess) return GPAIR_ERR_HIP;
+  return adjoint_records(p, delta, gA, gsigma, nullptr, s);
 }
 
 gpair_status gpair_adjoint_centres(gpair_plan p, const float *A, const float *sigma,
@@ -217,12 +249,8 @@ gpair_status gpair_adjoint_centres(gpair_plan p, const float *A, const float *si
                                    float *gcentres, gpair_stream stream) {
   if (!bound(p) || !A || !sigma || !delta || !gA || !gcentres) return GPAIR_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = launch_prep(p, A, sigma, s);
-  if (e != hipSuccess) return GPAIR_ERR_HIP;
-  timer_begin(p, GPAIR_TIMER_ADJOINT, s);
-  e = launch_adjoint(p, delta, gA, gsigma, gcentres, s);
-  timer_end(p, GPAIR_TIMER_ADJOINT, s);
-  return hip_status(e);
+  if (prep_direct(p, A, sigma, s) != hipSuccess) return GPAIR_ERR_HIP;
+  return adjoint_records(p, delta, gA, gsigma, gcentres, s);
 }
 
 gpair_status gpair_assa_grid_params(gpair_plan p, double sigma, gpair_assa_grid *out) {
@@ -257,6 +285,7 @@ gpair_status gpair_assa_forward(gpair_plan p, const float *x, double sigma, floa
   const gpair_status st = assa_grid(p, sigma, &g);
   if (st != GPAIR_OK) return st;
   hipStream_t s = (hipStream_t)stream;
+  p->prepared = 0;  // the ASSA prep overwrites the direct coefficients
   hipError_t e = launch_assa_prep(p, x, s);
   if (e == hipSuccess) e = launch_fill(y, (int64_t)p->Nd * p->Nt, 0.0f, s);
   if (e != hipSuccess) return GPAIR_ERR_HIP;

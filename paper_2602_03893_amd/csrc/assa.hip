@@ -269,13 +269,13 @@ __device__ __forceinline__ void conv_any(const int *icol, int c0, int nu, int al
 }
 
 // A, KK > 0: the grid (alpha, K) is fixed at compile time (register-window
-// convolution); A = 0: any grid.  The register budget is that of 7 waves per
-// SIMD (72 VGPRs, a few spills in the convolution), although the segment
-// already caps a CU at 3 workgroups (6 waves per SIMD): the schedule the
-// compiler makes for it ran 14% faster for (3, 12) and 10% for (2, 16) than
-// the unconstrained one (83 and 92 VGPRs) at the paper shape.
+// convolution); A = 0: any grid.  The register budget is that of 6 waves per
+// SIMD (80 VGPRs; 2 spills for (3, 12), 9 for (2, 16)), which the segment
+// already caps a CU at (3 workgroups): at the paper shape, (3, 12) measured
+// 7.24 ms against 7.55 ms at the budget of 7 waves (72 VGPRs, 7 spills) and
+// 9.5 ms unconstrained (83 VGPRs, no spills, 5 waves).
 template <int A, int KK>
-__global__ __launch_bounds__(kAssaWaves * kWave) __attribute__((amdgpu_waves_per_eu(7)))
+__global__ __launch_bounds__(kAssaWaves * kWave) __attribute__((amdgpu_waves_per_eu(6)))
 void assa_forward_kernel(
     const AssaRec *__restrict__ krec, AssaFwdArgs a) {
   extern __shared__ float seg[];  // [F][64]: fine row p of sensor column l at p*64 + l

@@ -132,7 +132,9 @@ constexpr int kXcds = 8;                // MI355X: 8 accelerator dies
 
 // Offsets (bytes) of each table inside the plan workspace.
 struct WorkspaceLayout {
-  size_t sens, perm, ftiles, atiles, krec, counters, partials, total;
+  size_t sens, perm, ftiles, atiles, krec, counters, partials;
+  size_t det;  // deterministic forward: int64 [Nd][Nt] trace accumulator (0 bytes otherwise)
+  size_t total;
 };
 
 struct HostTables {
@@ -155,6 +157,9 @@ struct gpair_plan_s {
   // tiling
   int32_t fwd_tile, adj_tile;
   int32_t fwd_waves;  // waves (sensor groups of 64) per forward workgroup
+  int32_t deterministic;  // forward flush through a global int64 fixed point
+  int32_t prepared;       // the records hold the direct operators' coefficients
+                          // (set by their prep, cleared by the ASSA prep)
   int32_t Lf, La;     // samples per forward / adjoint LDS segment
   double max_rho, min_dist;
   gpair::HostTables host;
@@ -178,7 +183,7 @@ namespace gpair {
 // that brings its truncation below kFilterIterTol samples, or -1 when the
 // filter's error bound is not below kFilterGuard / 2 (then the operators
 // decide every pair of the block in float64).
-constexpr double kFilterGuard = 0x1p-13;  // samples
+constexpr double kFilterGuard = 0x1p-14;  // samples
 constexpr double kFilterIterTol = 1e-6;   // samples
 constexpr int kFilterMaxSteps = 8;
 int filter_steps(double R, double rho, double inv_vdt, double hmax);
@@ -193,6 +198,8 @@ hipError_t launch_scale(float *x, int64_t n, float alpha, hipStream_t s);
 // (device); partial sums in the plan workspace.
 hipError_t launch_dot3(const gpair_plan_s *p, const float *y, const float *b, double *out,
                        hipStream_t s);
+// The forward into y (zeroed by the caller); with p->deterministic, y need
+// not be zeroed and the flush goes through the int64 accumulator.
 hipError_t launch_forward(const gpair_plan_s *p, float *y, hipStream_t s);
 // gsigma and gcentres may be null (not computed / not written).
 hipError_t launch_adjoint(const gpair_plan_s *p, const float *delta, float *gA,
@@ -248,6 +255,7 @@ inline unsigned long long *ws_counters(const gpair_plan_s *p) {
   return (unsigned long long *)(p->ws + p->lay.counters);
 }
 inline double *ws_partials(const gpair_plan_s *p) { return (double *)(p->ws + p->lay.partials); }
+inline long long *ws_det(const gpair_plan_s *p) { return (long long *)(p->ws + p->lay.det); }
 
 // Host planner (plan.cpp).
 gpair_status build_plan(const gpair_geometry *g, gpair_plan_s *p);
@@ -255,6 +263,6 @@ gpair_status build_plan(const gpair_geometry *g, gpair_plan_s *p);
 // sensor) pair of the forward (which = 0) or adjoint (1) tiling.
 gpair_status tiling_slots(const gpair_plan_s *p, int which, int64_t *min_first,
                           int64_t *max_last);
-WorkspaceLayout layout_for(int64_t M, int32_t Nd, size_t nft, size_t nat);
+WorkspaceLayout layout_for(int64_t M, int32_t Nd, size_t nft, size_t nat, int64_t det_words);
 
 }  // namespace gpair

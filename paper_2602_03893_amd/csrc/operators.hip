@@ -381,12 +381,16 @@ struct FwdArgs {
   double inv_vdt, t0_over_dt, hmax, vdt;
   double peak;      // bound of |A/(2r) d e^{-d^2/2 sigma^2}| r / |A| over sigma <= sigma_max
   double min_dist;  // lower bound of every kernel-sensor distance (m)
+  long long *y64;          // deterministic flush: int64 [Nd][Nt] in units of *det_unit
+  const double *det_unit;  // the global unit (device), set before the launch
 };
 
 // The record array is a direct kernel argument (const, restrict) so that its
 // uniform loads stay scalar loads next to the LDS adds of the tap loop.
-template <int WAVES>
-__global__ __launch_bounds__(WAVES * kWave) void forward_kernel(
+// Compiled for 8 waves per SIMD (64 VGPRs, no spills; 75 unconstrained, at
+// 6 waves, measured 1.3 % slower at the paper-scale shape).
+template <int WAVES, bool DET>
+__global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(8))) void forward_kernel(
     const KernelRec *__restrict__ krec, FwdArgs a) {
   extern __shared__ int seg[];  // [L][64]: sample-major, one column per sensor
   const int64_t logical = xcd_logical_block(a.nlogical);
@@ -457,14 +461,41 @@ __global__ __launch_bounds__(WAVES * kWave) void forward_kernel(
   }
   __syncthreads();
 
-  // Back to float32 (each lane's own unit), row c stored rotated by c columns
-  // so that the flush below reads a row of the transpose without bank
-  // conflicts.  Each row is read and rewritten by one wave.
+  // Back to float32 (each lane's own unit; DET: kept as integers), row c
+  // stored rotated by c columns so that the flush below reads a row of the
+  // transpose without bank conflicts.  Each row is read and rewritten by one
+  // wave.
   for (int cr = wave; cr < a.L; cr += WAVES) {
     const int v = col[cr * kWave];
-    seg[cr * kWave + ((lane + cr) & (kWave - 1))] = __float_as_int((float)v * unit);
+    seg[cr * kWave + ((lane + cr) & (kWave - 1))] = DET ? v : __float_as_int((float)v * unit);
   }
   __syncthreads();
+
+  if (DET) {
+    // Deterministic flush: each sample's tile sum (integer, in units of
+    // bound 2^-30) goes to the global unit G, rounded to the nearest integer,
+    // and is added with a 64-bit integer atomic.  The rounding depends only
+    // on the tile's own sum and integer addition is exact and commutative,
+    // so y is the same bit for bit whatever the order of the tiles.  G is
+    // 2^-62 of a bound on every sample of y, so no sum overflows.
+    const double G = *a.det_unit;
+    const double fac = bound * 0x1p-30 / G;
+    for (int row = wave; row < kWave; row += WAVES) {
+      const int jr = sg * kWave + row;
+      if (jr >= a.Nd) break;
+      const int nbr = __builtin_amdgcn_readlane(nb, row);
+      const double fr = __shfl(fac, row, kWave);
+      long long *yrow = a.y64 + (int64_t)jr * a.Nt;
+      for (int cs = lane; cs < a.L; cs += kWave) {
+        const int n = nbr + cs;
+        const int v = seg[cs * kWave + ((row + cs) & (kWave - 1))];
+        if (n >= 0 && n < a.Nt && v != 0)
+          __hip_atomic_fetch_add(yrow + n, (long long)llrint((double)v * fr), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    return;
+  }
 
   // Flush: one sensor row per wave at a time, lanes walk its samples so that
   // consecutive lanes add to consecutive addresses of y (coalesced float
@@ -644,8 +675,7 @@ __device__ __forceinline__ void adjoint_stage(const AdjPair &c, int nsb, float i
 }
 
 template <int BLOCK, int MODE>
-__global__ __launch_bounds__(BLOCK) void adjoint_kernel(const double4 *__restrict__ sens,
-                                                       AdjArgs a) {
+__device__ __forceinline__ void adjoint_body(const double4 *__restrict__ sens, const AdjArgs &a) {
   extern __shared__ float stage[];  // [kAdjSensorsPerStage][L]
   __shared__ int nbs[kAdjSensorsPerStage];
   __shared__ float4 su[kAdjSensorsPerStage];
@@ -779,6 +809,54 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(const double4 *__restric
   }
 }
 
+// The amplitude and sigma modes are held to the register budget of 7 waves
+// per SIMD (72 VGPRs, where they compile to 65-70); a variant that took 88
+// VGPRs ran at 5 waves and 7 % slower.  The centre mode keeps its ~98 VGPRs
+// (the cap would spill 19).
+template <int BLOCK, int MODE>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(7))) void adjoint_kernel(
+    const double4 *__restrict__ sens, AdjArgs a) {
+  adjoint_body<BLOCK, MODE>(sens, a);
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void adjoint_centres_kernel(const double4 *__restrict__ sens,
+                                                               AdjArgs a) {
+  adjoint_body<BLOCK, kAdjCentres>(sens, a);
+}
+
+// Deterministic forward: sum of |A_k| in float64 in a fixed order (block
+// partial sums, then one thread over the partials), and the global unit
+// G = 2^-62 sum |A| peak / min_dist, a bound of every sample of y over 2^62.
+__global__ __launch_bounds__(256) void det_abs_partial_kernel(const KernelRec *__restrict__ rec,
+                                                             int64_t M, double *partials) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < M; i += (int64_t)gridDim.x * 256)
+    acc += fabs((double)rec[i].amp);
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = sh[0];
+}
+
+__global__ void det_unit_kernel(const double *partials, int nblocks, double scale, double *unit) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double sum = 0.0;
+  for (int b = 0; b < nblocks; ++b) sum += partials[b];
+  *unit = sum * scale;
+}
+
+__global__ __launch_bounds__(256) void det_finish_kernel(const long long *__restrict__ y64,
+                                                        const double *unit, float *y, int64_t n) {
+  const double G = *unit;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    y[i] = (float)((double)y64[i] * G);
+}
+
 }  // namespace
 
 hipError_t launch_prep(const gpair_plan_s *p, const float *A, const float *sigma,
@@ -812,14 +890,37 @@ hipError_t launch_forward(const gpair_plan_s *p, float *y, hipStream_t s) {
   // the float32 rounding of the taps.
   a.peak = 0.5 * p->sigma_max * (1.0 + 1e-6) * 0.60653065971263342 * (1.0 + 1e-5);
   a.min_dist = p->min_dist;
+  a.y64 = nullptr;
+  a.det_unit = nullptr;
+  const int64_t n = (int64_t)p->Nd * p->Nt;
+  if (p->deterministic) {
+    a.y64 = ws_det(p);
+    double *unit = (double *)(a.y64 + n);
+    double *partials = ws_partials(p);
+    det_abs_partial_kernel<<<kResidualBlocks, 256, 0, s>>>(ws_krec(p), p->M, partials);
+    det_unit_kernel<<<1, 64, 0, s>>>(partials, kResidualBlocks, a.peak / a.min_dist * 0x1p-62,
+                                     unit);
+    a.det_unit = unit;
+    hipError_t e = launch_fill((float *)a.y64, 2 * n, 0.0f, s);  // int64 zero = two float zeros
+    if (e != hipSuccess) return e;
+  }
   const size_t lds = (size_t)p->Lf * kWave * sizeof(int);
   const unsigned int grid = xcd_grid(a.nlogical);
-  switch (p->fwd_waves) {
-    case 1: forward_kernel<1><<<grid, kWave, lds, s>>>(ws_krec(p), a); break;
-    case 2: forward_kernel<2><<<grid, 2 * kWave, lds, s>>>(ws_krec(p), a); break;
-    case 4: forward_kernel<4><<<grid, 4 * kWave, lds, s>>>(ws_krec(p), a); break;
-    default: forward_kernel<8><<<grid, 8 * kWave, lds, s>>>(ws_krec(p), a); break;
+#define GPAIR_FWD_LAUNCH(D)                                                                \
+  switch (p->fwd_waves) {                                                                  \
+    case 1: forward_kernel<1, D><<<grid, kWave, lds, s>>>(ws_krec(p), a); break;            \
+    case 2: forward_kernel<2, D><<<grid, 2 * kWave, lds, s>>>(ws_krec(p), a); break;        \
+    case 4: forward_kernel<4, D><<<grid, 4 * kWave, lds, s>>>(ws_krec(p), a); break;        \
+    default: forward_kernel<8, D><<<grid, 8 * kWave, lds, s>>>(ws_krec(p), a); break;       \
   }
+  if (p->deterministic) {
+    GPAIR_FWD_LAUNCH(true)
+    det_finish_kernel<<<(unsigned int)std::min<int64_t>((n + 255) / 256, 16384), 256, 0, s>>>(
+        a.y64, a.det_unit, y, n);
+  } else {
+    GPAIR_FWD_LAUNCH(false)
+  }
+#undef GPAIR_FWD_LAUNCH
   return hipGetLastError();
 }
 
@@ -852,7 +953,7 @@ hipError_t launch_adjoint(const gpair_plan_s *p, const float *delta, float *gA,
   switch (mode) {                                                                    \
     case kAdjA: adjoint_kernel<B, kAdjA><<<grid, B, lds, s>>>(sens, a); break;        \
     case kAdjSigma: adjoint_kernel<B, kAdjSigma><<<grid, B, lds, s>>>(sens, a); break; \
-    default: adjoint_kernel<B, kAdjCentres><<<grid, B, lds, s>>>(sens, a); break;     \
+    default: adjoint_centres_kernel<B><<<grid, B, lds, s>>>(sens, a); break;          \
   }
   switch (p->adj_tile) {
     case 64: GPAIR_ADJ_LAUNCH(64) break;

@@ -392,7 +392,7 @@ gpair_status tiling_slots(const gpair_plan_s *p, int which, int64_t *min_first,
   return GPAIR_OK;
 }
 
-WorkspaceLayout layout_for(int64_t M, int32_t Nd, size_t nft, size_t nat) {
+WorkspaceLayout layout_for(int64_t M, int32_t Nd, size_t nft, size_t nat, int64_t det_words) {
   WorkspaceLayout l{};
   size_t off = 0;
   l.sens = off;     off = align256(off + (size_t)Nd * 32);
@@ -402,6 +402,8 @@ WorkspaceLayout layout_for(int64_t M, int32_t Nd, size_t nft, size_t nat) {
   l.krec = off;     off = align256(off + (size_t)M * sizeof(KernelRec));
   l.counters = off; off = align256(off + 64);
   l.partials = off; off = align256(off + (size_t)kResidualBlocks * 3 * sizeof(double) + 64);
+  // det_words int64 accumulators, then the deterministic forward's global unit
+  l.det = off;      off = align256(off + (size_t)det_words * sizeof(long long) + (det_words ? 64 : 0));
   l.total = off;
   return l;
 }
@@ -581,7 +583,9 @@ gpair_status build_plan(const gpair_geometry *g, gpair_plan_s *p) {
   }
   p->min_dist = std::max(lbmin, near);
 
-  p->lay = layout_for(M, Nd, h.ftiles.size(), h.atiles.size());
+  p->deterministic = g->deterministic ? 1 : 0;
+  p->lay = layout_for(M, Nd, h.ftiles.size(), h.atiles.size(),
+                      p->deterministic ? (int64_t)Nd * g->n_samples : 0);
   return GPAIR_OK;
 }
 

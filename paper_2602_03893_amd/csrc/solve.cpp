@@ -148,7 +148,10 @@ gpair_status gpair_solve(gpair_plan p, const float *b, float *A, float *sigma,
   double rho = -1.0;
   for (; it < o->max_iters; ++it) {
     if (npc && launch_npc_map(M, z, npc_eps, A, s) != hipSuccess) return GPAIR_ERR_HIP;
-    st = gpair_forward(p, A, sigma, y, stream);
+    // (A, sigma) are the same for the forward and the adjoint of an
+    // iteration: their coefficient records are built once.
+    st = gpair_prepare(p, A, sigma, stream);
+    if (st == GPAIR_OK) st = gpair_forward_prepared(p, y, stream);
     if (st != GPAIR_OK) return st;
     if (launch_residual(p, y, b, scale, y, norms, s) != hipSuccess) return GPAIR_ERR_HIP;
     if (it % o->check_every == 0) {
@@ -163,7 +166,7 @@ gpair_status gpair_solve(gpair_plan p, const float *b, float *A, float *sigma,
         break;
       }
     }
-    st = gpair_adjoint(p, A, sigma, y, gA, gS, stream);
+    st = gpair_adjoint_prepared(p, y, gA, gS, stream);
     if (st != GPAIR_OK) return st;
     if (reg && launch_vcr(o->grid_nx, o->grid_ny, o->grid_nz, A, o->reg_beta, o->reg_eps,
                           o->reg_lambda, gA, nullptr, ws + L.vcr, s) != hipSuccess)

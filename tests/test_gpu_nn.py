@@ -403,3 +403,64 @@ def test_unet_train_step_applies_adam():
     losses = [host(net2.train_step(f32(x), tgt, lr=1e-4))[0] for _ in range(15)]
     _say(f"  loss {losses[0]:.4e} -> {losses[-1]:.4e}")
     assert losses[-1] < 0.9 * losses[0]
+
+
+def exact_regime_params(levels, seed):
+    """Sparse power-of-two weights (two of 1, 1/2 or -1/2 per output channel)
+    and biases in {0, 1/16, 1/8}: with inputs on a 1/4 grid and upstream
+    gradients on a 1/256 grid, every activation and activation-gradient sum
+    of the network is exact in float32 (the sum of |terms| stays below 2^24
+    of the smallest term's unit: checked on the oracle's values, tightest
+    margin 1.8x), so the GPU's float32 accumulation in any order gives the
+    oracle's exact sums and both round to the same bfloat16 values."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, kind, taps, ci, co in N.unet_layers(levels):
+        if kind == "head":
+            w = np.zeros(ci)
+            w[rng.choice(ci, 2, replace=False)] = rng.choice([1.0, 0.5], 2)
+            b = np.array([0.125])
+        else:
+            w = np.zeros((taps, ci, co))
+            for o in range(co):
+                for _ in range(2):
+                    w[rng.integers(taps), rng.integers(ci), o] = rng.choice([1.0, 0.5, 1.0, -0.5])
+            b = rng.choice([0.0, 0.0625, 0.125], co)
+        parts += [w.reshape(-1), b]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def test_unet_exact_regime_elementwise():
+    """The chained backward of the 4-level network pinned element by element:
+    in the exact-arithmetic regime above, the GPU forward must equal the
+    oracle's bfloat16-rounded forward bit for bit (so every ReLU sign and
+    max-pool argmax agrees), and every one of the 1.4 M parameter gradients
+    must meet the per-kernel rounding model |gpu - S| <= 2e-5 M + 1e-7 max|S|
+    (S the exact sum, M the sum of |terms|; the weight-gradient sums run over
+    up to 32768 voxels and are the only inexact float32 sums)."""
+    m = nn()
+    levels, shape = 4, (2, 16, 32, 32)
+    _say(f"case: unet levels {levels} shape {shape}, exact-arithmetic regime")
+    params = exact_regime_params(levels, 7)
+    rng = np.random.default_rng(8)
+    x = (rng.integers(0, 5, shape) * 0.25).astype(np.float32)
+    gy = (rng.integers(-128, 129, shape) / 256.0).astype(np.float32)
+    net = m.UNet(levels, shape, params=params)
+    y = host(net.forward(f32(x), scale=1.0))
+    y_ref, _ = N.unet_forward(levels, params, x)
+    n_diff = int(np.sum(y != y_ref.astype(np.float32)))
+    _say(f"  forward: {n_diff} of {y.size} outputs differ from the oracle")
+    assert n_diff == 0
+    g = host(net.backward(f32(gy)))
+    S, M = N.unet_backward(levels, params, x, gy.astype(np.float64), magnitudes=True)
+    bound = 2e-5 * M + 1e-7 * np.abs(S).max()
+    off = 0
+    worst = 0.0
+    for name, kind, taps, ci, co in N.unet_layers(levels):
+        nw = taps * ci * co + co
+        ratio = float(np.max(np.abs(g[off:off + nw] - S[off:off + nw]) / bound[off:off + nw]))
+        worst = max(worst, ratio)
+        _say(f"    {name:8s} max |gpu - S| / bound {ratio:.3f}, "
+             f"non-zero {np.count_nonzero(S[off:off + nw])} of {nw}")
+        off += nw
+    assert worst <= 1.0

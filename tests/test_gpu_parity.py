@@ -326,3 +326,54 @@ def test_filter_and_float64_blocks_in_one_plan():
     bar = dot_test_bound(Ax, delta)
     _say(f"  <Ax, y> {lhs:.9e}  <x, A^T y> {rhs:.9e}  |diff| {abs(lhs - rhs):.2e}  bar {bar:.2e}")
     assert abs(lhs - rhs) <= bar
+
+
+@pytest.mark.parametrize("name", ["toy", "paper"])
+def test_deterministic_forward_is_bitwise_reproducible(name):
+    """With the plan's deterministic flush, two forwards of the same input are
+    equal bit for bit (the float-atomic flush is not), and parity with the
+    oracle still holds."""
+    _say(f"case: deterministic forward, {name} workload")
+    w = I.WORKLOADS[name]
+    cen, sen = I.geometry_arrays(w)
+    from paper_2602_03893_amd import Plan
+    plan = Plan(cen, sen, w.n_samples, w.dt, w.c_sound, n_sigma=w.n_sigma, sigma_max=w.smax,
+                deterministic=True)
+    g = O.Geometry(cen, sen, w.n_samples, w.dt, w.t0, w.c_sound, w.n_sigma)
+    A = I.phantom(w)
+    if name == "toy":
+        A = (A * I.uniform(w.n_kernels, seed=26, lo=-1.0, hi=1.0)).astype(np.float32)
+    sigma = (w.sigma * I.uniform(w.n_kernels, seed=27, lo=0.9, hi=1.0)).astype(np.float32)
+    y1 = host(plan.forward(dev(A), dev(sigma)))
+    y2 = host(plan.forward(dev(A), dev(sigma)))
+    assert np.array_equal(y1, y2)
+    rows = np.arange(w.n_sensors) if name == "toy" else \
+        np.random.default_rng(28).choice(w.n_sensors, 16, replace=False)
+    ref = O.forward(g.subset_sensors(rows), A, sigma.astype(np.float64))
+    err = rel_l2(y1[rows], ref)
+    _say(f"  bitwise equal over two runs; forward rel L2 {err:.3e}")
+    assert err <= TOL
+
+
+def test_prepared_calls_match_and_are_refused_after_assa(toy):
+    """gpair_prepare + the _prepared operators give the one-call results (the
+    adjoint bit for bit; the forward to its float-atomic flush order), and a
+    _prepared call after an ASSA call on the plan is refused."""
+    from paper_2602_03893_amd import GpairError
+    w, plan, g = toy
+    A = I.uniform(w.n_kernels, seed=41, lo=-1.0, hi=1.0)
+    sigma = I.uniform(w.n_kernels, seed=42, lo=0.5 * w.sigma, hi=w.sigma)
+    delta = I.standard_normal((w.n_sensors, w.n_samples), seed=43)
+    y1 = host(plan.forward(dev(A), dev(sigma)))
+    a1, s1 = plan.adjoint(dev(A), dev(sigma), dev(delta))
+    a1, s1 = host(a1), host(s1)
+    plan.prepare(dev(A), dev(sigma))
+    y2 = host(plan.forward_prepared())
+    a2, s2 = plan.adjoint_prepared(dev(delta))
+    assert rel_l2(y2, y1) <= 1e-6
+    assert np.array_equal(host(a2), a1) and np.array_equal(host(s2), s1)
+    plan.assa_forward(dev(np.abs(A)), w.sigma)
+    with pytest.raises(GpairError, match="INVALID_ARG"):
+        plan.forward_prepared()
+    plan.prepare(dev(A), dev(sigma))
+    assert rel_l2(host(plan.forward_prepared()), y1) <= 1e-6
