@@ -239,6 +239,10 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--eval", type=int, default=5, help="held-out phantoms for time-to-rho")
+    ap.add_argument("--eval-first", type=int, default=100000,
+                    help="seed of the first held-out phantom")
+    ap.add_argument("--kappa", type=float, default=None,
+                    help="input normalisation of trained parameters (skips the power iteration)")
     ap.add_argument("--eval-iters", type=int, default=500)
     ap.add_argument("--workers", type=int, default=12)
     ap.add_argument("--train-budget", type=float, default=None, help="seconds")
@@ -255,7 +259,10 @@ def main(argv=None):
     pool = mp.get_context("fork").Pool(a.workers)
     import torch
     problem = Problem()
-    kappa = problem.power_kappa()
+    if a.kappa is not None:
+        problem.kappa = kappa = a.kappa
+    else:
+        kappa = problem.power_kappa()
     log(f"setup: kappa (largest eigenvalue of A_half^T A_half) = {kappa:.6e}")
     report = {"kappa": kappa, "levels": LEVELS}
     if a.params is None:
@@ -280,7 +287,8 @@ def main(argv=None):
     else:
         params = np.load(a.params, allow_pickle=False)
     if a.eval > 0:
-        report["eval"] = evaluate(problem, params, list(range(100000, 100000 + a.eval)),
+        report["eval"] = evaluate(problem, params,
+                                  list(range(a.eval_first, a.eval_first + a.eval)),
                                   max_iters=a.eval_iters, log=log)
     pool.close()
     pool.join()
