@@ -649,6 +649,9 @@ def main():
                    "kernels": M, "sensors": Nd, "samples": Nt, "parallelism": "single GPU"},
         "fwd_kernel_ms": t_fwd,
         "adj_kernel_ms": t_adj,
+        "paper_context": {"gpu": "RTX 5090", "operators": "ASSA (shared sigma, no sigma "
+                          "gradient)", "fwd_ms": PAPER_ASSA_MS["forward"],
+                          "adj_ms": PAPER_ASSA_MS["adjoint"]},
         "taps_per_operator": taps,
         "taps_per_s": 2 * taps * args.steps / elapsed,
         "plan_s": t_plan,
