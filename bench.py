@@ -361,7 +361,8 @@ def bench_assa(args):
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": MEASURED_TRAFFIC_ASSA.get(kernel_source_hash("assa.hip"), {})
-                                                     .get("assa_forward_kernel")},
+                                                     .get("assa_forward_kernel"),
+                     "kernel_source_sha256_16": kernel_source_hash("assa.hip")},
     }
     if obj:
         out.update(objective_fields(obj, w))
@@ -663,7 +664,8 @@ def main():
                      "exp_per_s": exp_rate,
                      "exp_frac_of_measured": exp_rate / (peaks["v_exp_f32"]["wave_instr_per_s"] * 64),
                      "valu_per_cu_per_clk": MEASURED_VALU.get(kernel_source_hash(), {}).get(dom),
-                     "measured_peaks": peaks},
+                     "measured_peaks": peaks,
+                     "kernel_source_sha256_16": kernel_source_hash()},
     }
     if obj:
         out.update(objective_fields(obj, w))

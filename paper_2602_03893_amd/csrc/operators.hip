@@ -156,14 +156,18 @@ struct PairW {
   bool last_ok;
 };
 
-// The float32 filter; returns true when a decision is within kGuard of its
-// boundary (then the caller decides again with pair_exact).
-__device__ __forceinline__ bool pair_filter(const BlockLane &bl, int kit, float dx, float dy,
-                                            float dz, float dd, float hf, float H,
-                                            float inv_vdt_f, PairW &p) {
-  const float D = fmaf(bl.m2ux, dx, fmaf(bl.m2uy, dy, fmaf(bl.m2uz, dz, dd)));
-  float dr = D * bl.inv2R;
-  for (int it = 0; it < kit; ++it) dr = fmaf(-dr, dr, D) * bl.inv2R;
+// The float32 filter in three parts: D = r^2 - R^2 from the record's offset
+// dk = c - c_B and |dk|^2 (dx, dy, dz, dd); kit fixed-point steps of
+// dr = (D - dr^2)/(2R) towards r - R; the window from dr.  The last returns
+// true when a decision is within kGuard of its boundary (then the caller
+// decides again with pair_exact).
+__device__ __forceinline__ float filter_D(const BlockLane &bl, float dx, float dy, float dz,
+                                          float dd) {
+  return fmaf(bl.m2ux, dx, fmaf(bl.m2uy, dy, fmaf(bl.m2uz, dz, dd)));
+}
+
+__device__ __forceinline__ bool filter_window(const BlockLane &bl, float dr, float hf, float H,
+                                              float inv_vdt_f, PairW &p) {
   const float zf = fmaf(dr, inv_vdt_f, bl.Xf - hf);
   const float cz = ceilf(zf);
   const float e = zf - cz;  // in (-1, 0]
@@ -173,6 +177,15 @@ __device__ __forceinline__ bool pair_filter(const BlockLane &bl, int kit, float 
   p.rinv = __builtin_amdgcn_rcpf(bl.Rf + dr);
   const float m = fminf(fminf(fabsf(e), fabsf(e + 1.0f)), fabsf(e - H));
   return m < kGuard;
+}
+
+__device__ __forceinline__ bool pair_filter(const BlockLane &bl, int kit, float dx, float dy,
+                                            float dz, float dd, float hf, float H,
+                                            float inv_vdt_f, PairW &p) {
+  const float D = filter_D(bl, dx, dy, dz, dd);
+  float dr = D * bl.inv2R;
+  for (int it = 0; it < kit; ++it) dr = fmaf(-dr, dr, D) * bl.inv2R;
+  return filter_window(bl, dr, hf, H, inv_vdt_f, p);
 }
 
 // The float64 decision: r from the caller's float32 coordinates, the first
@@ -216,14 +229,8 @@ struct FwdLoop {
   float iuw;  // fixed-point units per unit of A/r d/Delta: 2^30/B * Delta/2
 };
 
-template <bool EXACT>
-__device__ __forceinline__ Taps pair_taps(const FwdLoop &c, const KernelRec &r) {
-  PairW p;
-  if (EXACT) {
-    pair_exact<true>(c.s, r.fcx, r.fcy, r.fcz, r.h, r.ntap, c.nb, c.inv_vdt, c.t0_over_dt, p);
-  } else if (pair_filter(c.bl, c.kit, r.dx, r.dy, r.dz, r.dd, r.hf, r.H, c.inv_vdt_f, p)) {
-    pair_exact<false>(c.s, r.fcx, r.fcy, r.fcz, r.h, r.ntap, c.nb, c.inv_vdt, c.t0_over_dt, p);
-  }
+// The tap setup of one pair from its window.
+__device__ __forceinline__ Taps taps_of(const FwdLoop &c, const KernelRec &r, const PairW &p) {
   Taps t;
   t.d = p.d0;
   t.o = p.o;
@@ -232,6 +239,44 @@ __device__ __forceinline__ Taps pair_taps(const FwdLoop &c, const KernelRec &r) 
   t.f = t.w * __builtin_amdgcn_exp2f(r.c * t.d * t.d);
   t.q = __builtin_amdgcn_exp2f(fmaf(r.k1, t.d, r.c));
   return t;
+}
+
+template <bool EXACT>
+__device__ __forceinline__ Taps pair_taps(const FwdLoop &c, const KernelRec &r) {
+  PairW p;
+  if (EXACT) {
+    pair_exact<true>(c.s, r.fcx, r.fcy, r.fcz, r.h, r.ntap, c.nb, c.inv_vdt, c.t0_over_dt, p);
+  } else if (pair_filter(c.bl, c.kit, r.dx, r.dy, r.dz, r.dd, r.hf, r.H, c.inv_vdt_f, p)) {
+    pair_exact<false>(c.s, r.fcx, r.fcy, r.fcz, r.h, r.ntap, c.nb, c.inv_vdt, c.t0_over_dt, p);
+  }
+  return taps_of(c, r, p);
+}
+
+// Two pairs at once: the filter's steps of both run in one loop.
+template <bool EXACT>
+__device__ __forceinline__ void pair_taps2(const FwdLoop &c, const KernelRec &ra,
+                                           const KernelRec &rb, Taps &ta, Taps &tb) {
+  if (EXACT) {
+    ta = pair_taps<true>(c, ra);
+    tb = pair_taps<true>(c, rb);
+    return;
+  }
+  const float Da = filter_D(c.bl, ra.dx, ra.dy, ra.dz, ra.dd);
+  const float Db = filter_D(c.bl, rb.dx, rb.dy, rb.dz, rb.dd);
+  float dra = Da * c.bl.inv2R, drb = Db * c.bl.inv2R;
+  for (int it = 0; it < c.kit; ++it) {
+    dra = fmaf(-dra, dra, Da) * c.bl.inv2R;
+    drb = fmaf(-drb, drb, Db) * c.bl.inv2R;
+  }
+  PairW pa, pb;
+  if (filter_window(c.bl, dra, ra.hf, ra.H, c.inv_vdt_f, pa))
+    pair_exact<false>(c.s, ra.fcx, ra.fcy, ra.fcz, ra.h, ra.ntap, c.nb, c.inv_vdt, c.t0_over_dt,
+                      pa);
+  if (filter_window(c.bl, drb, rb.hf, rb.H, c.inv_vdt_f, pb))
+    pair_exact<false>(c.s, rb.fcx, rb.fcy, rb.fcz, rb.h, rb.ntap, c.nb, c.inv_vdt, c.t0_over_dt,
+                      pb);
+  ta = taps_of(c, ra, pa);
+  tb = taps_of(c, rb, pb);
 }
 
 // Add v (in fixed-point units) to an LDS word, rounded half up with one
@@ -244,22 +289,32 @@ __device__ __forceinline__ void lds_add(int *p, float v) {
 
 // Add the taps of one kernel-sensor pair into the lane's segment column p
 // (stride 64 words), f already in fixed-point units: NT samples, of which the
-// first nvalid are inside the window (nvalid = ntap - 1 or ntap, and ntap >=
-// NT - 2, so only the last three can be outside).
-template <int NT>
-__device__ __forceinline__ void taps_add(int *p, float f, float q, float d, float rq,
-                                         int nvalid) {
+// first ntap - 1 are inside the window and tap ntap - 1 is inside iff last_ok.
+// The kernel's tap count ntap (wave-uniform) lies in NT - SPREAD .. NT, so
+// only the last SPREAD + 1 samples can be outside: taps from ntap on by a
+// uniform test, tap ntap - 1 by the lane's own.
+template <int NT, int SPREAD>
+__device__ __forceinline__ void taps_add(int *p, float f, float q, float d, float rq, int ntap,
+                                         bool last_ok) {
+  // t_i = f_i u_i with u_{i+1} = u_i - 1, f_{i+1} = f_i q_i: then
+  // t_{i+1} = q_i t_i - f_{i+1}, one fused multiply-add per tap.
   float t[NT];
+  t[0] = f * d;
 #pragma unroll
-  for (int i = 0; i < NT; ++i) {
-    t[i] = f * d;
-    d -= 1.0f;
+  for (int i = 0; i + 1 < NT; ++i) {
     f *= q;
+    t[i + 1] = fmaf(q, t[i], -f);
     q *= rq;
   }
+  if (SPREAD == 0) {
+    if (!last_ok) t[NT - 1] = 0.0f;
+  } else {
 #pragma unroll
-  for (int i = (NT - 3 > 0 ? NT - 3 : 0); i < NT; ++i)
-    if (i >= nvalid) t[i] = 0.0f;
+    for (int i = (NT - 1 - SPREAD > 0 ? NT - 1 - SPREAD : 0); i < NT; ++i) {
+      const bool inside = i < ntap - 1 || (i == ntap - 1 && last_ok);
+      if (!inside) t[i] = 0.0f;
+    }
+  }
 #pragma unroll
   for (int i = 0; i < NT; ++i) lds_add(p + i * kWave, t[i]);
 }
@@ -275,10 +330,9 @@ constexpr int kTapRun = 16;
 // record, read again only there).
 __device__ __forceinline__ void taps_add_n(int n, int *p, const Taps &t, float rq,
                                            const KernelRec *rec) {
-  const int nvalid = n - (t.last_ok ? 0 : 1);
   switch (n) {
 #define GPAIR_TAPS_CASE(k) \
-  case k: taps_add<k>(p, t.f, t.q, t.d, rq, nvalid); return;
+  case k: taps_add<k, 0>(p, t.f, t.q, t.d, rq, k, t.last_ok); return;
     GPAIR_TAPS_CASE(1) GPAIR_TAPS_CASE(2) GPAIR_TAPS_CASE(3) GPAIR_TAPS_CASE(4)
     GPAIR_TAPS_CASE(5) GPAIR_TAPS_CASE(6) GPAIR_TAPS_CASE(7) GPAIR_TAPS_CASE(8)
     GPAIR_TAPS_CASE(9) GPAIR_TAPS_CASE(10) GPAIR_TAPS_CASE(11) GPAIR_TAPS_CASE(12)
@@ -288,6 +342,7 @@ __device__ __forceinline__ void taps_add_n(int n, int *p, const Taps &t, float r
     default: break;
   }
   const float c = rec->c, k1 = rec->k1;
+  const int nvalid = n - (t.last_ok ? 0 : 1);
   for (int i0 = 0; i0 < n; i0 += kTapRun) {
     float d = t.d - (float)i0;
     float f = t.w * __builtin_amdgcn_exp2f(c * d * d);
@@ -303,29 +358,29 @@ __device__ __forceinline__ void taps_add_n(int n, int *p, const Taps &t, float r
 }
 
 // The kernel loop of one wave over records [k0, kend) of one reference
-// block when every kernel of the tile has NT - 2 .. NT taps.  Kernels go in
-// pairs: both pair stages sit in one straight-line block, so their chains
+// block when every kernel of the tile has NT - SPREAD .. NT taps.  Kernels go
+// in pairs: both pair stages sit in one straight-line block, so their chains
 // interleave, and the records of the next pair are fetched meanwhile
 // (clamped to the last record).
-template <int NT, bool EXACT>
+template <int NT, int SPREAD, bool EXACT>
 __device__ __forceinline__ void kernel_loop(const FwdLoop &c, int *col, int k0, int kend) {
   if (k0 >= kend) return;
   const int last = kend - 1;
   const int pend = k0 + ((kend - k0) & ~1);
   KernelRec ra = c.krec[k0], rb = c.krec[min(k0 + 1, last)];
   for (int k = k0; k < pend; k += 2) {
-    const Taps ta = pair_taps<EXACT>(c, ra);
-    const Taps tb = pair_taps<EXACT>(c, rb);
+    Taps ta, tb;
+    pair_taps2<EXACT>(c, ra, rb, ta, tb);
     const float rqa = ra.rq, rqb = rb.rq;
-    const int nva = ra.ntap - (ta.last_ok ? 0 : 1), nvb = rb.ntap - (tb.last_ok ? 0 : 1);
+    const int na = ra.ntap, nb = rb.ntap;
     ra = c.krec[min(k + 2, last)];
     rb = c.krec[min(k + 3, last)];
-    taps_add<NT>(col + ta.o * kWave, ta.f, ta.q, ta.d, rqa, nva);
-    taps_add<NT>(col + tb.o * kWave, tb.f, tb.q, tb.d, rqb, nvb);
+    taps_add<NT, SPREAD>(col + ta.o * kWave, ta.f, ta.q, ta.d, rqa, na, ta.last_ok);
+    taps_add<NT, SPREAD>(col + tb.o * kWave, tb.f, tb.q, tb.d, rqb, nb, tb.last_ok);
   }
   if (pend < kend) {
     const Taps t = pair_taps<EXACT>(c, ra);
-    taps_add<NT>(col + t.o * kWave, t.f, t.q, t.d, ra.rq, ra.ntap - (t.last_ok ? 0 : 1));
+    taps_add<NT, SPREAD>(col + t.o * kWave, t.f, t.q, t.d, ra.rq, ra.ntap, t.last_ok);
   }
 }
 
@@ -356,10 +411,14 @@ __device__ __forceinline__ void kernel_loop_mixed(const FwdLoop &c, int *col, in
 
 template <bool EXACT>
 __device__ __forceinline__ void block_loops(const FwdLoop &c, int *col, int k0, int k1,
-                                            int nt_unrolled) {
+                                            int nt_unrolled, int spread) {
   switch (nt_unrolled) {
-#define GPAIR_FWD_CASE(n) \
-  case n: kernel_loop<n, EXACT>(c, col, k0, k1); break;
+#define GPAIR_FWD_CASE(n)                                                      \
+  case n:                                                                      \
+    if (spread == 0) kernel_loop<n, 0, EXACT>(c, col, k0, k1);                 \
+    else if (spread == 1) kernel_loop<n, 1, EXACT>(c, col, k0, k1);            \
+    else kernel_loop<n, 2, EXACT>(c, col, k0, k1);                             \
+    break;
     GPAIR_FWD_CASE(2) GPAIR_FWD_CASE(3) GPAIR_FWD_CASE(4) GPAIR_FWD_CASE(5)
     GPAIR_FWD_CASE(6) GPAIR_FWD_CASE(7) GPAIR_FWD_CASE(8) GPAIR_FWD_CASE(9)
     GPAIR_FWD_CASE(10) GPAIR_FWD_CASE(11) GPAIR_FWD_CASE(12) GPAIR_FWD_CASE(13)
@@ -449,15 +508,16 @@ __global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(8
   c.inv_vdt_f = (float)a.inv_vdt;
   c.iuw = bound > 0.0 ? (float)(0x1p30 / bound * 0.5 * a.vdt) : 0.0f;
   const int nt_unrolled = (nmin >= nmax - 2 && nmax >= 2 && nmax <= 18) ? nmax : 0;
+  const int spread = nmax - nmin;
   const int bend = tile + 1 < a.ntiles ? a.tiles[tile + 1].first_block : a.nblocks;
   for (int b = T.first_block + wave; b < bend; b += WAVES) {
     const TileInfo B = a.blocks[b];
     block_lane(s, B, nb, a.inv_vdt, a.t0_over_dt, c.bl);
     c.kit = B.filter_steps;
     if (c.kit < 0)
-      block_loops<true>(c, col, B.start, B.start + B.count, nt_unrolled);
+      block_loops<true>(c, col, B.start, B.start + B.count, nt_unrolled, spread);
     else
-      block_loops<false>(c, col, B.start, B.start + B.count, nt_unrolled);
+      block_loops<false>(c, col, B.start, B.start + B.count, nt_unrolled, spread);
   }
   __syncthreads();
 
@@ -539,20 +599,29 @@ constexpr int kAdjRankMinSensors = 256;
 constexpr int kAdjA = 0, kAdjSigma = 1, kAdjCentres = 2;
 
 // Gather the taps of one kernel-sensor pair from a staged residual row (row
-// points at the pair's first sample): NT samples of which the first nvalid
-// are in the window (only the last three can be outside).  All reads are
-// issued first.  With t = delta f (f = e/r) and offsets u in samples:
-// s1 += t u, and for MODE >= 1 s3 += t u^3, for MODE 2 s0 += t, s2 += t u^2.
-template <int NT, int MODE>
+// points at the pair's first sample): NT samples, of which the first
+// ntap - 1 are in the window and sample ntap - 1 is iff last_ok.  The wave's
+// tap counts lie in NT - SPREAD .. NT, so only the last SPREAD + 1 samples
+// can be outside (with SPREAD = 0 only the last, by last_ok alone).  All
+// reads are issued first.  With t = delta f (f = e/r) and offsets u in
+// samples: s1 += t u, and for MODE >= 1 s3 += t u^3, for MODE 2 s0 += t,
+// s2 += t u^2.
+template <int NT, int SPREAD, int MODE>
 __device__ __forceinline__ void gather_taps(const float *row, float f, float q, float d,
-                                            float rq, int nvalid, float &s0, float &s1,
-                                            float &s2, float &s3) {
+                                            float rq, int ntap, bool last_ok, float &s0,
+                                            float &s1, float &s2, float &s3) {
   float dl[NT];
 #pragma unroll
   for (int i = 0; i < NT; ++i) dl[i] = row[i];
+  if (SPREAD == 0) {
+    if (!last_ok) dl[NT - 1] = 0.0f;
+  } else {
 #pragma unroll
-  for (int i = (NT - 3 > 0 ? NT - 3 : 0); i < NT; ++i)
-    if (i >= nvalid) dl[i] = 0.0f;
+    for (int i = (NT - 1 - SPREAD > 0 ? NT - 1 - SPREAD : 0); i < NT; ++i) {
+      const bool inside = i < ntap - 1 || (i == ntap - 1 && last_ok);
+      if (!inside) dl[i] = 0.0f;
+    }
+  }
 #pragma unroll
   for (int i = 0; i < NT; ++i) {
     if (MODE == kAdjCentres) {
@@ -597,18 +666,18 @@ struct AdjPair {
 };
 
 // The taps of one stage of sensors for one lane's kernel.  NT > 0: every
-// kernel of the wave has NT - 2 .. NT taps (fully unrolled); NT = 0: any.
+// kernel of the wave has NT - SPREAD .. NT taps (fully unrolled); NT = 0: any.
 // isg2 = (Delta/sigma_k)^2 (MODE 2).
-template <int NT, int MODE>
+template <int NT, int SPREAD, int MODE>
 __device__ __forceinline__ void adjoint_stage(const AdjPair &c, int nsb, float isg2,
                                               AdjSums &acc) {
   const KernelRec &r = *c.r;
   for (int js = 0; js < nsb; ++js) {
+    // One sensor for the whole wave: U, V and the segment base are uniform;
+    // the base is read only on the float64 path.
     const float4 U = c.su[js];
     const float4 V = c.sv[js];
-    // One sensor for the whole wave: these are uniform.
     const int kit = c.kit;
-    const int nb = __builtin_amdgcn_readfirstlane(c.nbs[js]);
     PairW p;
     if (kit >= 0) {
       BlockLane bl;
@@ -618,16 +687,15 @@ __device__ __forceinline__ void adjoint_stage(const AdjPair &c, int nsb, float i
       bl.inv2R = U.w;
       bl.Rf = V.x;
       bl.Xf = V.y;
-      bl.Xi = __builtin_amdgcn_readfirstlane(__float_as_int(V.z));
+      bl.Xi = __float_as_int(V.z);
       if (pair_filter(bl, kit, r.dx, r.dy, r.dz, r.dd, r.hf, r.H, c.inv_vdt_f, p))
-        pair_exact<false>(c.sens[c.j0 + js], r.fcx, r.fcy, r.fcz, r.h, r.ntap, nb, c.inv_vdt,
-                          c.t0_over_dt, p);
+        pair_exact<false>(c.sens[c.j0 + js], r.fcx, r.fcy, r.fcz, r.h, r.ntap, c.nbs[js],
+                          c.inv_vdt, c.t0_over_dt, p);
     } else {
-      pair_exact<true>(c.sens[c.j0 + js], r.fcx, r.fcy, r.fcz, r.h, r.ntap, nb, c.inv_vdt,
+      pair_exact<true>(c.sens[c.j0 + js], r.fcx, r.fcy, r.fcz, r.h, r.ntap, c.nbs[js], c.inv_vdt,
                        c.t0_over_dt, p);
     }
     const float d0 = p.d0;
-    const int nvalid = p.last_ok ? r.ntap : r.ntap - 1;
     const float f = p.rinv * __builtin_amdgcn_exp2f(r.c * d0 * d0);
     const float q = __builtin_amdgcn_exp2f(fmaf(r.k1, d0, r.c));
     const float *row = c.stage + js * c.L + p.o;
@@ -637,8 +705,10 @@ __device__ __forceinline__ void adjoint_stage(const AdjPair &c, int nsb, float i
     float &s1 = MODE == kAdjCentres ? t1 : acc.a;
     float &s3 = MODE == kAdjCentres ? t3 : acc.s;
     if (NT > 0) {
-      gather_taps<(NT > 0 ? NT : 1), MODE>(row, f, q, d0, r.rq, nvalid, t0, s1, t2, s3);
+      gather_taps<(NT > 0 ? NT : 1), SPREAD, MODE>(row, f, q, d0, r.rq, r.ntap, p.last_ok, t0, s1,
+                                                   t2, s3);
     } else {
+      const int nvalid = p.last_ok ? r.ntap : r.ntap - 1;
       // Any tap count: the Gaussian factors are re-evaluated every kTapRun
       // taps, as in the forward.
       for (int i0 = 0; i0 < nvalid; i0 += kTapRun) {
@@ -721,6 +791,7 @@ __device__ __forceinline__ void adjoint_body(const double4 *__restrict__ sens, c
   const int nmax = __builtin_amdgcn_readfirstlane(wave_max(live ? r.ntap : 0));
   const int nmin = __builtin_amdgcn_readfirstlane(wave_min(live ? r.ntap : 1 << 30));
   const int NT = (nmax >= 2 && nmax <= 18 && nmin >= nmax - 2) ? nmax : 0;
+  const int spread = nmax - nmin;
 
   AdjPair c;
   c.sens = sens;
@@ -772,14 +843,18 @@ __device__ __forceinline__ void adjoint_body(const double4 *__restrict__ sens, c
     c.j0 = j0;
     AdjSums sums = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     switch (NT) {
-#define GPAIR_ADJ_CASE(n) \
-  case n: adjoint_stage<n, MODE>(c, nsb, isg2, sums); break;
+#define GPAIR_ADJ_CASE(n)                                                       \
+  case n:                                                                       \
+    if (spread == 0) adjoint_stage<n, 0, MODE>(c, nsb, isg2, sums);             \
+    else if (spread == 1) adjoint_stage<n, 1, MODE>(c, nsb, isg2, sums);        \
+    else adjoint_stage<n, 2, MODE>(c, nsb, isg2, sums);                         \
+    break;
       GPAIR_ADJ_CASE(2) GPAIR_ADJ_CASE(3) GPAIR_ADJ_CASE(4) GPAIR_ADJ_CASE(5)
       GPAIR_ADJ_CASE(6) GPAIR_ADJ_CASE(7) GPAIR_ADJ_CASE(8) GPAIR_ADJ_CASE(9)
       GPAIR_ADJ_CASE(10) GPAIR_ADJ_CASE(11) GPAIR_ADJ_CASE(12) GPAIR_ADJ_CASE(13)
       GPAIR_ADJ_CASE(14) GPAIR_ADJ_CASE(15) GPAIR_ADJ_CASE(16) GPAIR_ADJ_CASE(17)
       GPAIR_ADJ_CASE(18)
-      default: adjoint_stage<0, MODE>(c, nsb, isg2, sums); break;
+      default: adjoint_stage<0, 2, MODE>(c, nsb, isg2, sums); break;
 #undef GPAIR_ADJ_CASE
     }
     accA += (double)sums.a;
