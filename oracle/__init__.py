@@ -31,8 +31,17 @@ Pins (what each function is checked against, in ``tests/``):
  - ``ops.adjoint_centres``  central differences of the pinned forward in float32
                      centres; torch autograd of an independent torch
                      formulation over the same windows.
+ - ``ops.forward_aniso`` / ``ops.adjoint_aniso``  (anisotropic kernels) the
+                     isotropic case against ``ops.forward`` / ``ops.adjoint``;
+                     exact axis permutations and reflections; the closed form
+                     of ``physics`` at every sample; convergence to the
+                     numerical Poisson integral of the anisotropic p0 as
+                     sigma/r -> 0; the dot-product test; central differences
+                     in the six covariance parameters
+                     (tests/test_oracle_aniso.py).
  - ``physics``       Gauss-Legendre quadrature of the surface integral and a
-                     numerical derivative of Eq. (pa_wave).
+                     numerical derivative of Eq. (pa_wave) (isotropic and
+                     anisotropic p0).
  - ``solvers.pgd``   converges to scipy's NNLS solution (a different algorithm).
  - ``solvers.adam``  matches torch.optim.Adam (a library implementation) step by
                      step on the same gradients.

@@ -290,3 +290,139 @@ void oracle_assa_adjoint(int64_t m, const float *cx, const float *cy, const floa
   }
   free(h);
 }
+
+/* ------------------------------------------------------------------------
+ * Anisotropic kernels (learnable anisotropic Gaussians, named as future work
+ * in the paper's Discussion).  Kernel k has p0 = A_k exp(-(x - c_k)^T
+ * Sigma_k^-1 (x - c_k) / 2) with Sigma_k symmetric positive definite, given
+ * as six numbers (xx, yy, zz, xy, xz, yz).  Reading of the far field: the
+ * detector's sphere is taken as flat across the kernel (the same far-field
+ * step that keeps only the outgoing term in Eq. (single_forward)), so the
+ * surface integral of p0 is the kernel's marginal along n = (s - c)/r:
+ * 2 pi sqrt(det Sigma)/sigma_n exp(-d^2/(2 sigma_n^2)), sigma_n^2 = n^T Sigma
+ * n, and Eq. (pa_wave) gives
+ *     p = A sqrt(det Sigma)/sigma_n^3 * d/(2r) * exp(-d^2/(2 sigma_n^2)),
+ * inside |d| <= n_sigma sigma_n.  With Sigma = sigma^2 I this is
+ * Eq. (single_forward) exactly.
+ * ------------------------------------------------------------------------ */
+
+/* det and sigma_n^2 of one pair: q = u^T Sigma u / |u|^2 with u = s - c. */
+static double aniso_det(const double *S) {
+  double xx = S[0], yy = S[1], zz = S[2], xy = S[3], xz = S[4], yz = S[5];
+  return xx * (yy * zz - yz * yz) - xy * (xy * zz - yz * xz) + xz * (xy * yz - yy * xz);
+}
+
+static double aniso_sn2(const double *S, double ux, double uy, double uz, double r2) {
+  double q = S[0] * ux * ux + S[1] * uy * uy + S[2] * uz * uz +
+             2.0 * (S[3] * ux * uy + S[4] * ux * uz + S[5] * uy * uz);
+  return q / r2;
+}
+
+/* Forward: y[j*nt + n] = sum_k [|d| <= nsig sigma_n] p_k(s_j, t_n), p as
+ * above.  sigma6 float64 [m][6]; y float64 [nd][nt], overwritten. */
+void oracle_forward_aniso(int64_t m, const float *cx, const float *cy, const float *cz,
+                          const double *amp, const double *sigma6, int64_t nd,
+                          const float *sensors, int64_t nt, double dt, double t0, double v,
+                          double nsig, double *y) {
+  int64_t j;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (j = 0; j < nd; ++j) {
+    double *row = y + j * nt;
+    for (int64_t n = 0; n < nt; ++n) row[n] = 0.0;
+    const float *s = sensors + 3 * j;
+    for (int64_t k = 0; k < m; ++k) {
+      const double *S = sigma6 + 6 * k;
+      double ux = (double)s[0] - (double)cx[k];
+      double uy = (double)s[1] - (double)cy[k];
+      double uz = (double)s[2] - (double)cz[k];
+      double r2 = ux * ux + uy * uy + uz * uz;
+      double r = sqrt(r2);
+      double sn2 = aniso_sn2(S, ux, uy, uz, r2);
+      double sn = sqrt(sn2);
+      double half = nsig * sn;
+      double a = amp[k] * sqrt(aniso_det(S)) / (sn2 * sn);
+      int64_t lo, hi;
+      candidate_range(r, half, v, dt, t0, nt, &lo, &hi);
+      for (int64_t n = lo; n <= hi; ++n) {
+        double t = t0 + (double)n * dt;
+        double d = r - v * t;
+        if (fabs(d) <= half) row[n] += a / (2.0 * r) * d * exp(-(d * d) / (2.0 * sn2));
+      }
+    }
+  }
+}
+
+/* Adjoint and the gradient with respect to Sigma.  With w = sqrt(det)/
+ * sigma_n^3 /(2r) and the window held fixed:
+ *   gA[k] = sum_j sum_{n in W} delta w d e,
+ *   dp/dSigma = p [Sigma^-1 / 2 + (d^2/(2 sigma_n^4) - 3/(2 sigma_n^2)) n n^T]
+ * (d sqrt(det)/dSigma = sqrt(det) Sigma^-1 / 2, d sigma_n^2/dSigma = n n^T),
+ * reported for the six parameters (xx, yy, zz, xy, xz, yz) of the symmetric
+ * matrix: an off-diagonal parameter stands for two entries, so its gradient
+ * is twice the matrix entry's.  delta float64 [nd][nt]; gA float64 [m];
+ * gsig6 float64 [m][6] or NULL. */
+void oracle_adjoint_aniso(int64_t m, const float *cx, const float *cy, const float *cz,
+                          const double *amp, const double *sigma6, int64_t nd,
+                          const float *sensors, int64_t nt, double dt, double t0, double v,
+                          double nsig, const double *delta, double *ga, double *gsig6) {
+  int64_t k;
+#pragma omp parallel for schedule(static)
+  for (k = 0; k < m; ++k) {
+    const double *S = sigma6 + 6 * k;
+    double det = aniso_det(S);
+    double sq = sqrt(det);
+    double acc_a = 0.0;
+    double acc_n[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t j = 0; j < nd; ++j) {
+      const float *s = sensors + 3 * j;
+      double ux = (double)s[0] - (double)cx[k];
+      double uy = (double)s[1] - (double)cy[k];
+      double uz = (double)s[2] - (double)cz[k];
+      double r2 = ux * ux + uy * uy + uz * uz;
+      double r = sqrt(r2);
+      double sn2 = aniso_sn2(S, ux, uy, uz, r2);
+      double sn = sqrt(sn2);
+      double half = nsig * sn;
+      double w = sq / (sn2 * sn) / (2.0 * r);
+      int64_t lo, hi;
+      candidate_range(r, half, v, dt, t0, nt, &lo, &hi);
+      double s1 = 0.0, s3 = 0.0;
+      for (int64_t n = lo; n <= hi; ++n) {
+        double t = t0 + (double)n * dt;
+        double d = r - v * t;
+        if (fabs(d) <= half) {
+          double e = exp(-(d * d) / (2.0 * sn2));
+          double dl = delta[j * nt + n];
+          s1 += dl * d * e;
+          s3 += dl * d * d * d * e;
+        }
+      }
+      acc_a += w * s1;
+      /* the n n^T part: A w [s3/(2 sn^4) - 3 s1/(2 sn^2)] n n^T */
+      double g = w * (s3 / (2.0 * sn2 * sn2) - 3.0 * s1 / (2.0 * sn2)) / r2;
+      acc_n[0] += g * ux * ux;
+      acc_n[1] += g * uy * uy;
+      acc_n[2] += g * uz * uz;
+      acc_n[3] += g * ux * uy;
+      acc_n[4] += g * ux * uz;
+      acc_n[5] += g * uy * uz;
+    }
+    ga[k] = acc_a;
+    if (gsig6) {
+      double a = amp[k];
+      double xx = S[0], yy = S[1], zz = S[2], xy = S[3], xz = S[4], yz = S[5];
+      /* Sigma^-1 by cofactors */
+      double i_xx = (yy * zz - yz * yz) / det, i_yy = (xx * zz - xz * xz) / det;
+      double i_zz = (xx * yy - xy * xy) / det, i_xy = (xz * yz - xy * zz) / det;
+      double i_xz = (xy * yz - xz * yy) / det, i_yz = (xy * xz - xx * yz) / det;
+      double h = 0.5 * a * acc_a;  /* sum delta p times 1/2 */
+      double *o = gsig6 + 6 * k;
+      o[0] = h * i_xx + a * acc_n[0];
+      o[1] = h * i_yy + a * acc_n[1];
+      o[2] = h * i_zz + a * acc_n[2];
+      o[3] = 2.0 * (h * i_xy + a * acc_n[3]);
+      o[4] = 2.0 * (h * i_xz + a * acc_n[4]);
+      o[5] = 2.0 * (h * i_yz + a * acc_n[5]);
+    }
+  }
+}

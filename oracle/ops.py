@@ -13,7 +13,13 @@ Definitions (arXiv 2602.03893, Methods):
  - adjoint: the transpose of that linear map ("Adjoint Operator" subsection);
  - sigma-gradient: d/dsigma of Eq. (single_forward), A d^3 e / (2 r sigma^3);
  - centre gradient: d/dc_k of Eq. (single_forward) through r = |s - c_k|
-   (learnable centres, the paper's stated future work), window held fixed.
+   (learnable centres, the paper's stated future work), window held fixed;
+ - anisotropic kernels (the other half of that future work): the far-field
+   pressure of p0 = A exp(-(x-c)^T Sigma^-1 (x-c)/2), the kernel's marginal
+   along the sensor direction n, A sqrt(det Sigma)/sigma_n^3 d/(2r)
+   exp(-d^2/(2 sigma_n^2)), sigma_n^2 = n^T Sigma n, inside |d| <= n_sigma
+   sigma_n; its transpose, and its gradient with respect to the six
+   parameters (xx, yy, zz, xy, xz, yz) of Sigma, window held fixed.
 """
 import ctypes
 import os
@@ -54,6 +60,13 @@ def _load():
     lib.oracle_count_taps.argtypes = [_i64, _f32p, _f32p, _f32p, _f64p, _i64,
                                       _f32p, _i64, _dbl, _dbl, _dbl, _dbl,
                                       ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
+    lib.oracle_forward_aniso.restype = None
+    lib.oracle_forward_aniso.argtypes = [_i64, _f32p, _f32p, _f32p, _f64p, _f64p,
+                                         _i64, _f32p, _i64, _dbl, _dbl, _dbl, _dbl, _f64p]
+    lib.oracle_adjoint_aniso.restype = None
+    lib.oracle_adjoint_aniso.argtypes = [_i64, _f32p, _f32p, _f32p, _f64p, _f64p,
+                                         _i64, _f32p, _i64, _dbl, _dbl, _dbl, _dbl,
+                                         _f64p, _f64p, ctypes.c_void_p]
     lib.oracle_num_threads.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
     _lib = lib
@@ -163,3 +176,41 @@ def count_taps(g: Geometry, sigma):
                           g.sensors, g.n_samples, g.dt, g.t0, g.c_sound,
                           g.n_sigma, ctypes.byref(taps), ctypes.byref(pairs))
     return int(taps.value), int(pairs.value)
+
+
+def _sigma6(sigma6, n):
+    s = np.ascontiguousarray(np.asarray(sigma6, dtype=np.float64).reshape(-1, 6))
+    if s.shape[0] != n:
+        raise ValueError(f"sigma6: expected ({n}, 6), got {s.shape}")
+    return s
+
+
+def forward_aniso(g: Geometry, amp, sigma6):
+    """y[j, n] (float64, (N_d, N_t)) of anisotropic kernels; sigma6 is (M, 6):
+    the covariance entries (xx, yy, zz, xy, xz, yz) in m^2."""
+    lib = _load()
+    a = _vec(amp, g.n_kernels, "amp")
+    s = _sigma6(sigma6, g.n_kernels)
+    y = np.empty((g.n_sensors, g.n_samples), dtype=np.float64)
+    lib.oracle_forward_aniso(g.n_kernels, g.cx, g.cy, g.cz, a, s, g.n_sensors, g.sensors,
+                             g.n_samples, g.dt, g.t0, g.c_sound, g.n_sigma, y)
+    return y
+
+
+def adjoint_aniso(g: Geometry, amp, sigma6, delta, want_sigma=True):
+    """(gA [M], gSigma (M, 6) or None) of anisotropic kernels: the transpose
+    of forward_aniso, and the gradient of <forward_aniso, delta> with respect
+    to the six covariance parameters (an off-diagonal parameter stands for
+    both symmetric entries)."""
+    lib = _load()
+    a = _vec(amp, g.n_kernels, "amp")
+    s = _sigma6(sigma6, g.n_kernels)
+    d = np.ascontiguousarray(np.asarray(delta, dtype=np.float64))
+    if d.shape != (g.n_sensors, g.n_samples):
+        raise ValueError(f"delta: expected {(g.n_sensors, g.n_samples)}, got {d.shape}")
+    ga = np.empty(g.n_kernels, dtype=np.float64)
+    gs = np.empty((g.n_kernels, 6), dtype=np.float64) if want_sigma else None
+    lib.oracle_adjoint_aniso(g.n_kernels, g.cx, g.cy, g.cz, a, s, g.n_sensors, g.sensors,
+                             g.n_samples, g.dt, g.t0, g.c_sound, g.n_sigma, d, ga,
+                             gs.ctypes.data_as(ctypes.c_void_p) if gs is not None else None)
+    return ga, gs

@@ -110,3 +110,59 @@ def pressure_poisson_cloud(amps, centres, sigma, t, v, half_width=0.08,
 
     deriv = (-g(t + 2 * h) + 8 * g(t + h) - 8 * g(t - h) + g(t - 2 * h)) / (12 * h)
     return deriv / (4.0 * np.pi * v)
+
+
+def pressure_poisson_aniso(amp, centre, cov, t, v, half_width=None, nodes=320,
+                           rel_step=2e-3):
+    """Eq. (pa_wave) for one anisotropic Gaussian p0 = A exp(-(x-c)^T cov^-1
+    (x-c)/2) with the detector at the origin: two-dimensional Gauss-Legendre
+    quadrature of p0 over the patch of the sphere |x| = v t around the
+    direction of c (polar angle about that direction up to where p0 is below
+    exp(-40) on the sphere, full azimuth), and a fourth-order central
+    difference in t.  No closed form is used."""
+    c = np.asarray(centre, dtype=np.float64)
+    cov = np.asarray(cov, dtype=np.float64)
+    icov = np.linalg.inv(cov)
+    r = float(np.linalg.norm(c))
+    e3 = c / r
+    # an orthonormal frame (e1, e2, e3) with e3 along c
+    a = np.array([1.0, 0.0, 0.0]) if abs(e3[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    e1 = a - e3 * np.dot(a, e3)
+    e1 /= np.linalg.norm(e1)
+    e2 = np.cross(e3, e1)
+    smax = float(np.sqrt(np.max(np.linalg.eigvalsh(cov))))
+    if half_width is None:
+        half_width = min(np.pi, 12.0 * smax / r)
+    th, wth = _gauss_legendre(nodes, 0.0, half_width)
+    ph, wph = _gauss_legendre(nodes, 0.0, 2.0 * np.pi)
+    TH, PH = np.meshgrid(th, ph, indexing="ij")
+    W = np.outer(wth, wph) * np.sin(TH)
+    unit = (np.sin(TH)[..., None] * (np.cos(PH)[..., None] * e1 + np.sin(PH)[..., None] * e2)
+            + np.cos(TH)[..., None] * e3)
+
+    def surface_integral(rp):
+        x = rp * unit - c
+        q = np.einsum("...i,ij,...j->...", x, icov, x)
+        return rp * rp * np.sum(W * amp * np.exp(-0.5 * q))
+
+    h = rel_step * np.sqrt(np.min(np.linalg.eigvalsh(cov))) / v
+
+    def g(tt):
+        return surface_integral(v * tt) / (v * tt)
+
+    deriv = (-g(t + 2 * h) + 8 * g(t + h) - 8 * g(t - h) + g(t - 2 * h)) / (12 * h)
+    return deriv / (4.0 * np.pi * v)
+
+
+def pressure_far_aniso(amp, centre, cov, t, v):
+    """The far-field closed form of the anisotropic kernel (detector at the
+    origin): A sqrt(det cov)/sigma_n^3 d/(2r) exp(-d^2/(2 sigma_n^2)) with
+    n = -c/r the direction from the kernel to the detector (sigma_n is even
+    in n), sigma_n^2 = n^T cov n, d = r - v t."""
+    c = np.asarray(centre, dtype=np.float64)
+    cov = np.asarray(cov, dtype=np.float64)
+    r = float(np.linalg.norm(c))
+    n = c / r
+    sn2 = float(n @ cov @ n)
+    d = r - v * t
+    return amp * np.sqrt(np.linalg.det(cov)) / sn2 ** 1.5 * d / (2.0 * r) * np.exp(-d * d / (2.0 * sn2))
