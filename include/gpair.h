@@ -285,9 +285,51 @@ gpair_status gpair_adjoint_prepared(gpair_plan p, const float *delta, float *gA,
                                     float *gsigma, gpair_stream stream);
 
 /*
+ * Anisotropic kernels (learnable anisotropic Gaussians, the other half of the
+ * future work named in the paper's Discussion).  Kernel k has initial
+ * pressure A_k exp(-(x - c_k)^T Sigma_k^-1 (x - c_k) / 2) with a symmetric
+ * positive definite covariance Sigma_k.  Far-field reading: the detector's
+ * sphere is flat across the kernel (the step that keeps only the outgoing
+ * term of Eq. (single_forward)), so Eq. (pa_wave) integrates the kernel's
+ * marginal along n = (s_j - c_k)/r and gives
+ *   p = A_k sqrt(det Sigma_k)/sigma_n^3 * d/(2r) * exp(-d^2/(2 sigma_n^2)),
+ *   sigma_n^2 = n^T Sigma_k n, d = r - v t, inside |d| <= n_sigma sigma_n,
+ * which is Eq. (single_forward) exactly when Sigma_k = sigma^2 I; its
+ * relative error against the full sphere integral falls like sigma/r (about
+ * 2e-3 at 40 mm for axes up to 0.1 mm).
+ *  A       device float32 [n_kernels] (gpair_adjoint_aniso reads it only when
+ *          gsigma6 != NULL; it may then be NULL otherwise).
+ *  sigma6  device float32 [6][n_kernels] (structure of arrays): the entries
+ *          xx, yy, zz, xy, xz, yz of Sigma_k in m^2.  A covariance that is not
+ *          positive definite or whose largest eigenvalue exceeds sigma_max^2
+ *          is replaced by sigma_max^2 I for that kernel and counted (see
+ *          gpair_sigma_violations); the call still returns GPAIR_OK.
+ *  y       device float32 [n_sensors][n_samples], overwritten (forward; float
+ *          atomics: the plan's `deterministic` option does not apply here).
+ *  delta   device float32 [n_sensors][n_samples] (adjoint).
+ *  gA      device float32 [n_kernels], overwritten: the transpose of the
+ *          forward applied to delta.
+ *  gsigma6 device float32 [6][n_kernels], overwritten, or NULL to skip: the
+ *          gradient of <forward, delta> with respect to the six parameters at
+ *          fixed windows, dp/dSigma = p [Sigma^-1/2 + (d^2/(2 sigma_n^4) -
+ *          3/(2 sigma_n^2)) n n^T], an off-diagonal parameter carrying both
+ *          symmetric entries (twice the matrix entry).
+ * Each pair's window is decided in float64; sums over sensors are carried in
+ * float64.  These calls overwrite the direct operators' per-kernel
+ * coefficients (a _prepared call after them returns INVALID_ARG).
+ * Errors: INVALID_ARG, HIP.
+ */
+gpair_status gpair_forward_aniso(gpair_plan p, const float *A, const float *sigma6, float *y,
+                                 gpair_stream stream);
+gpair_status gpair_adjoint_aniso(gpair_plan p, const float *A, const float *sigma6,
+                                 const float *delta, float *gA, float *gsigma6,
+                                 gpair_stream stream);
+
+/*
  * Synchronise `stream` and return in *count how many sigma_k values outside
- * (0, sigma_max] the operators have met since the plan was created (each
- * forward/adjoint call adds its count).  Errors: INVALID_ARG, HIP.
+ * (0, sigma_max] (and anisotropic covariances outside the admitted set) the
+ * operators have met since the plan was created (each forward/adjoint call
+ * adds its count).  Errors: INVALID_ARG, HIP.
  */
 gpair_status gpair_sigma_violations(gpair_plan p, int64_t *count,
                                     gpair_stream stream);

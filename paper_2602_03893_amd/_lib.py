@@ -112,6 +112,9 @@ gpair_prepare = _proto("gpair_prepare", c_i32, [c_vp, c_vp, c_vp, c_vp])
 gpair_forward_prepared = _proto("gpair_forward_prepared", c_i32, [c_vp, c_vp, c_vp])
 gpair_adjoint_prepared = _proto("gpair_adjoint_prepared", c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp])
 gpair_adjoint = _proto("gpair_adjoint", c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp])
+gpair_forward_aniso = _proto("gpair_forward_aniso", c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp])
+gpair_adjoint_aniso = _proto("gpair_adjoint_aniso", c_i32,
+                             [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp])
 gpair_adjoint_centres = _proto("gpair_adjoint_centres", c_i32,
                                [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp])
 gpair_sigma_violations = _proto("gpair_sigma_violations", c_i32,

@@ -192,6 +192,34 @@ class Plan:
               "gpair_adjoint_centres")
         return gA, gS, gC
 
+    def forward_aniso(self, A, sigma6, out=None):
+        """y (N_d, N_t) float32 of anisotropic kernels (gpair_forward_aniso);
+        sigma6 is (6, M): the covariance entries xx, yy, zz, xy, xz, yz (m^2)."""
+        M = self.n_kernels
+        pa = _dev(A, "A", M, device=self.device)
+        ps = _dev(sigma6, "sigma6", 6 * M, device=self.device)
+        if out is None:
+            out = torch.empty((self.n_sensors, self.n_samples), dtype=torch.float32,
+                              device=self.device)
+        py = _dev(out, "y", self.n_sensors * self.n_samples, device=self.device)
+        check(_lib.gpair_forward_aniso(self._h, pa, ps, py, _stream()), "gpair_forward_aniso")
+        return out
+
+    def adjoint_aniso(self, A, sigma6, delta, want_sigma=True):
+        """(gA [M], gsigma6 (6, M) or None) float32 of anisotropic kernels
+        (gpair_adjoint_aniso)."""
+        M = self.n_kernels
+        ps = _dev(sigma6, "sigma6", 6 * M, device=self.device)
+        pd = _dev(delta, "delta", self.n_sensors * self.n_samples, device=self.device)
+        pa = _dev(A, "A", M, device=self.device) if (want_sigma or A is not None) else None
+        gA = torch.empty(M, dtype=torch.float32, device=self.device)
+        gS = torch.empty((6, M), dtype=torch.float32, device=self.device) if want_sigma else None
+        check(_lib.gpair_adjoint_aniso(self._h, pa, ps, pd, _dev(gA, "gA", M),
+                                       _dev(gS, "gsigma6", 6 * M) if want_sigma else None,
+                                       _stream()),
+              "gpair_adjoint_aniso")
+        return gA, gS
+
     def residual(self, y, b, scale=1.0, delta=None):
         """norms (2,) float64 on device = (sum (y-b)^2, sum b^2); writes
         delta = scale (y - b) when `delta` is given (may be y itself)."""

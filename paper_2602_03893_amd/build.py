@@ -19,7 +19,7 @@ LIB = os.path.join(PKG, "libgpair.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["plan.cpp", "api.cpp", "solve.cpp", "operators.hip", "vector_ops.hip", "assa.hip",
-           "assa_static.hip", "objective.hip", "peaks.hip",
+           "assa_static.hip", "objective.hip", "peaks.hip", "aniso.hip",
            "nn_api.cpp", "nn_ops.hip", "unet.cpp"]
 
 COMMON = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",

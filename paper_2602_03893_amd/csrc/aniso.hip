@@ -1,0 +1,452 @@
+// aniso.hip -- gfx950 kernels of the direct operators for anisotropic
+// Gaussian kernels (learnable anisotropic Gaussians: the future work named in
+// the Discussion of arXiv 2602.03893).
+//
+// Kernel k has p0 = A_k exp(-(x - c_k)^T Sigma_k^-1 (x - c_k) / 2), Sigma_k
+// given as six numbers (xx, yy, zz, xy, xz, yz).  Far field: the detector's
+// sphere is taken as flat across the kernel (the same step that keeps only
+// the outgoing term of Eq. (single_forward)), so the sphere integral of p0 is
+// the kernel's marginal along n = (s - c)/r and Eq. (pa_wave) gives
+//     p = A sqrt(det Sigma) / sigma_n^3 * d / (2r) * exp(-d^2 / (2 sigma_n^2)),
+//     sigma_n^2 = n^T Sigma n,  d = r - v t,  kept inside |d| <= n_sigma sigma_n
+// (Eq. (single_forward) exactly when Sigma = sigma^2 I).  The window depends
+// on the pair through sigma_n, so each pair is decided in float64 (distance,
+// sigma_n, first and last in-window sample, as the float64 definition) and
+// its taps run in float32 with the same Gaussian recurrence as the isotropic
+// operators, re-evaluated every kTapRunAniso taps.
+//
+// Forward: one workgroup per (forward tile, 64 sensors), lane = sensor, the
+// waves take the tile's kernels in turn (wave-uniform loop); taps go into
+// the shared fixed-point LDS segment of the tile's time shell as in the
+// isotropic forward (the same segment bounds hold since every sigma_n is at
+// most sigma_max), then one float atomic per sample into y.
+// Adjoint: one workgroup per adjoint tile, lane = kernel; per stage of 64
+// sensors the residual over the tile's time shell is staged in LDS; per pair
+// the lane gathers its taps.  float32 within a stage, float64 across stages.
+// Gradient with respect to the six covariance parameters at fixed windows:
+//   dp/dSigma = p [Sigma^-1 / 2 + (d^2 / (2 sigma_n^4) - 3 / (2 sigma_n^2)) n n^T],
+// an off-diagonal parameter standing for both symmetric entries (twice the
+// matrix entry).
+#include <cmath>
+
+#include "gpair_internal.h"
+
+namespace gpair {
+namespace {
+
+// The 64-byte record as the anisotropic operators use it (rebuilt by their
+// prep on every call; the geometry fields are shared with KernelRec).
+struct alignas(64) AnisoRec {
+  float dx, dy, dz, dd;                // geometry (unused here)
+  float sxx, syy, szz, sxy, sxz, syz;  // covariance (m^2)
+  float A;                             // amplitude
+  float fcz;                           // geometry: float32 centre (z)
+  float sq;                            // sqrt(det Sigma)
+  float pk;                            // |A| sqrt(det) / lambda_min bound: |A| sqrt(det) tr^2 / (4 det)
+  float fcx, fcy;                      // geometry: float32 centre (x, y)
+};
+static_assert(sizeof(AnisoRec) == 64, "AnisoRec layout");
+static_assert(offsetof(AnisoRec, fcz) == offsetof(KernelRec, fcz) &&
+                  offsetof(AnisoRec, fcx) == offsetof(KernelRec, fcx) &&
+                  offsetof(AnisoRec, fcy) == offsetof(KernelRec, fcy) &&
+                  offsetof(AnisoRec, dd) == offsetof(KernelRec, dd),
+              "shared geometry fields");
+
+constexpr int kAnisoWaves = 4;   // forward waves per workgroup
+constexpr int kTapRunAniso = 16; // taps between exact Gaussian factors
+constexpr double kLog2eA = 1.4426950408889634;
+
+__device__ __forceinline__ int64_t xcd_logical_a(int64_t nlogical) {
+  const int64_t per = (nlogical + kXcds - 1) / kXcds;
+  const int64_t b = blockIdx.x;
+  return (b % kXcds) * per + b / kXcds;
+}
+
+inline unsigned int xcd_grid_a(int64_t nlogical) {
+  const int64_t per = (nlogical + kXcds - 1) / kXcds;
+  return (unsigned int)(per * kXcds);
+}
+
+// ---------------------------------------------------------------------------
+// Records: covariance checks, sqrt(det), the fixed-point bound factor.
+// ---------------------------------------------------------------------------
+// A covariance is admitted when it is symmetric positive definite (leading
+// minors > 0) and smax2 I - Sigma is positive semidefinite (every principal
+// minor >= 0), i.e. its largest eigenvalue is at most smax2.  Anything else
+// is counted and replaced by smax2 I for that kernel.
+__global__ __launch_bounds__(256) void aniso_prep_kernel(
+    const float *__restrict__ A, const float *__restrict__ sig6,
+    const int32_t *__restrict__ perm, AnisoRec *__restrict__ rec, int64_t M, double smax2,
+    unsigned long long *viol) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= M) return;
+  const int32_t k = perm[i];
+  float s[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) s[c] = sig6[(int64_t)c * M + k];
+  double xx = s[0], yy = s[1], zz = s[2], xy = s[3], xz = s[4], yz = s[5];
+  double det = xx * (yy * zz - yz * yz) - xy * (xy * zz - yz * xz) + xz * (xy * yz - yy * xz);
+  const bool spd = xx > 0.0 && xx * yy - xy * xy > 0.0 && det > 0.0;
+  // B = smax2 I - Sigma: its off-diagonal entries are -xy, -xz, -yz.
+  const double bxx = smax2 - xx, byy = smax2 - yy, bzz = smax2 - zz;
+  const double bdet =
+      bxx * (byy * bzz - yz * yz) - xy * (xy * bzz + yz * xz) - xz * (xy * yz + byy * xz);
+  const bool below = bxx >= 0.0 && byy >= 0.0 && bzz >= 0.0 && bxx * byy - xy * xy >= 0.0 &&
+                     bxx * bzz - xz * xz >= 0.0 && byy * bzz - yz * yz >= 0.0 && bdet >= 0.0;
+  if (!(spd && below)) {
+    atomicAdd(viol, 1ULL);
+    xx = yy = zz = smax2;
+    xy = xz = yz = 0.0;
+    det = smax2 * smax2 * smax2;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) s[c] = c < 3 ? (float)smax2 : 0.0f;
+  }
+  const float a = A ? A[k] : 0.0f;
+  const double sq = sqrt(det);
+  const double tr = xx + yy + zz;
+  AnisoRec &r = rec[i];
+  r.sxx = s[0];
+  r.syy = s[1];
+  r.szz = s[2];
+  r.sxy = s[3];
+  r.sxz = s[4];
+  r.syz = s[5];
+  r.A = a;
+  r.sq = (float)sq;
+  r.pk = (float)(fabs((double)a) * sq * tr * tr / (4.0 * det));
+}
+
+// One pair's window and tap constants.  u = s - c in float64; sigma_n^2 is
+// clamped to smax2 (the records admit no more; the clamp only absorbs
+// rounding), so the window never exceeds the plan's widest.
+struct AnisoPair {
+  double ux, uy, uz, r2, r;
+  double sn2;      // sigma_n^2 (m^2)
+  int64_t lo;      // first in-window sample
+  int ntap;        // in-window samples (>= 0)
+  float d0;        // offset of sample lo from the pulse centre, samples
+  float c, k1, rq; // exp2(c u^2) = exp(-d^2/(2 sigma_n^2)); ratio constants
+};
+
+__device__ __forceinline__ void aniso_pair(const double4 &s, const AnisoRec &k, double inv_vdt,
+                                           double t0_over_dt, double nsig, double smax2,
+                                           AnisoPair &p) {
+  p.ux = s.x - (double)k.fcx;
+  p.uy = s.y - (double)k.fcy;
+  p.uz = s.z - (double)k.fcz;
+  p.r2 = fma(p.uz, p.uz, fma(p.uy, p.uy, p.ux * p.ux));
+  p.r = sqrt(p.r2);
+  const double q = (double)k.sxx * p.ux * p.ux + (double)k.syy * p.uy * p.uy +
+                   (double)k.szz * p.uz * p.uz +
+                   2.0 * ((double)k.sxy * p.ux * p.uy + (double)k.sxz * p.ux * p.uz +
+                          (double)k.syz * p.uy * p.uz);
+  double sn2 = q / p.r2;
+  sn2 = (sn2 > 0.0 && sn2 <= smax2) ? sn2 : smax2;
+  p.sn2 = sn2;
+  const double hs = nsig * sqrt(sn2) * inv_vdt;
+  const double nc = fma(p.r, inv_vdt, -t0_over_dt);
+  const double lo = ceil(nc - hs);
+  const double hi = floor(nc + hs);
+  p.lo = (int64_t)lo;
+  p.ntap = hi >= lo ? (int)(hi - lo) + 1 : 0;
+  p.d0 = (float)(nc - lo);
+  const double su2 = sn2 * inv_vdt * inv_vdt;  // sigma_n^2 in samples^2
+  const double c = -kLog2eA / (2.0 * su2);
+  p.c = (float)c;
+  p.k1 = (float)(-2.0 * c);
+  p.rq = (float)exp2(2.0 * c);
+}
+
+// ---------------------------------------------------------------------------
+// Forward.
+// ---------------------------------------------------------------------------
+struct AnisoFwdArgs {
+  const double4 *sens;
+  const TileInfo *tiles;
+  float *y;
+  int64_t nlogical;
+  int32_t Nd, Nt, nsg, L;
+  double inv_vdt, t0_over_dt, hmax, vdt, nsig, smax2, min_dist;
+};
+
+__device__ __forceinline__ void lds_add_fx(int *p, float v) {
+  int n;
+  asm volatile("v_cvt_rpi_i32_f32 %0, %1" : "=v"(n) : "v"(v));
+  __hip_atomic_fetch_add(p, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * kWave) void aniso_forward_kernel(
+    const AnisoRec *__restrict__ rec, AnisoFwdArgs a) {
+  extern __shared__ int seg[];  // [L][64]
+  const int64_t logical = xcd_logical_a(a.nlogical);
+  if (logical >= a.nlogical) return;
+  const int64_t tile = logical / a.nsg;
+  const int sg = (int)(logical - tile * a.nsg);
+  const int t = threadIdx.x;
+  const int lane = t & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int j = sg * kWave + lane;
+  const double4 s = a.sens[j < a.Nd ? j : a.Nd - 1];
+  const TileInfo T = a.tiles[tile];
+  double R;
+  {
+    const double dx = s.x - T.cx, dy = s.y - T.cy, dz = s.z - T.cz;
+    R = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
+  }
+  const int nb = (int)floor((R - T.rho) * a.inv_vdt - a.t0_over_dt - a.hmax) - 1;
+  for (int i = t; i < a.L * kWave; i += WAVES * kWave) seg[i] = 0;
+
+  // Fixed-point unit: every tap of kernel k at distance r is at most
+  // pk_k e^{-1/2} / (2 r) in magnitude, so B = e^{-1/2}/(2 r_low) sum pk
+  // bounds any sample's tile sum; every wave adds the same values in the same
+  // order, so all waves use the same unit.
+  float psum = 0.0f;
+  for (int i = T.start + lane; i < T.start + T.count; i += kWave) psum += rec[i].pk;
+  for (int off = 32; off > 0; off >>= 1) psum += __shfl_xor(psum, off, kWave);
+  const double r_low = fmax(R - T.rho, a.min_dist);
+  const double bound = (double)psum * (1.0 + 1e-5) * 0.60653065971263342 / (2.0 * r_low);
+  const float unit = (float)(bound * 0x1p-30);
+  const double iuw = bound > 0.0 ? 0x1p30 / bound : 0.0;
+  __syncthreads();
+
+  // Slots: o = lo - nb >= 1 and o + ntap - 1 <= L - 1 for every pair (the
+  // plan's slot bound with the widest admitted window, which no sigma_n
+  // exceeds); the clamps keep the masked taps past a short window, which the
+  // wave runs up to its longest, inside the segment.
+  int *const col = seg + lane;
+  const int Lm1 = a.L - 1;
+  for (int k = T.start + wave; k < T.start + T.count; k += WAVES) {
+    const AnisoRec r = rec[k];
+    AnisoPair p;
+    aniso_pair(s, r, a.inv_vdt, a.t0_over_dt, a.nsig, a.smax2, p);
+    // p = A sq / sigma_n^3 * (u Delta) / (2r) * exp2(c u^2), u in samples
+    const double w = (double)r.A * (double)r.sq / (p.sn2 * sqrt(p.sn2)) * (a.vdt / (2.0 * p.r)) * iuw;
+    const int o = (int)(p.lo - nb);
+    const int n = p.ntap;
+    int nmax = n;
+    for (int off = 32; off > 0; off >>= 1) nmax = max(nmax, __shfl_xor(nmax, off, kWave));
+    for (int i0 = 0; i0 < nmax; i0 += kTapRunAniso) {
+      float d = p.d0 - (float)i0;
+      float f = (float)w * __builtin_amdgcn_exp2f(p.c * d * d);
+      float q = __builtin_amdgcn_exp2f(fmaf(p.k1, d, p.c));
+      const int iend = min(i0 + kTapRunAniso, nmax);
+      for (int i = i0; i < iend; ++i) {
+        const float v = i < n ? f * d : 0.0f;
+        lds_add_fx(col + min(max(o + i, 0), Lm1) * kWave, v);
+        d -= 1.0f;
+        f *= q;
+        q *= p.rq;
+      }
+    }
+  }
+  __syncthreads();
+
+  // Back to float32 (each lane's own unit), row c rotated by c columns, then
+  // one coalesced float atomic per sample (as the isotropic forward).
+  for (int cr = wave; cr < a.L; cr += WAVES) {
+    const int v = col[cr * kWave];
+    seg[cr * kWave + ((lane + cr) & (kWave - 1))] = __float_as_int((float)v * unit);
+  }
+  __syncthreads();
+  for (int row = wave; row < kWave; row += WAVES) {
+    const int jr = sg * kWave + row;
+    if (jr >= a.Nd) break;
+    const int nbr = __builtin_amdgcn_readlane(nb, row);
+    float *yrow = a.y + (int64_t)jr * a.Nt;
+    for (int cs = lane; cs < a.L; cs += kWave) {
+      const int n = nbr + cs;
+      const float v = __int_as_float(seg[cs * kWave + ((row + cs) & (kWave - 1))]);
+      if (n >= 0 && n < a.Nt && v != 0.0f) unsafeAtomicAdd(yrow + n, v);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint.
+// ---------------------------------------------------------------------------
+struct AnisoAdjArgs {
+  const AnisoRec *rec;
+  const TileInfo *tiles;
+  const int32_t *perm;
+  const float *delta;
+  float *gA;
+  float *gS;  // [6][M] caller order, or null
+  int64_t nlogical, M;
+  int32_t Nd, Nt, L;
+  double inv_vdt, t0_over_dt, hmax, vdt, nsig, smax2;
+};
+
+template <int BLOCK, bool SIGMA>
+__global__ __launch_bounds__(BLOCK) void aniso_adjoint_kernel(const double4 *__restrict__ sens,
+                                                              AnisoAdjArgs a) {
+  extern __shared__ float stage[];  // [kAdjSensorsPerStage][L]
+  __shared__ int nbs[kAdjSensorsPerStage];
+
+  const int64_t logical = xcd_logical_a(a.nlogical);
+  if (logical >= a.nlogical) return;
+  const TileInfo T = a.tiles[logical];
+  const int t = threadIdx.x;
+  const int lane = t & (kWave - 1);
+  const int wave = t >> 6;
+  const bool live = t < T.count;
+  const int64_t i = T.start + (live ? t : 0);
+  const AnisoRec r = a.rec[i];
+  const int Lm1 = a.L - 1;
+
+  double accA = 0.0, accN[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int j0 = 0; j0 < a.Nd; j0 += kAdjSensorsPerStage) {
+    const int nsb = min(kAdjSensorsPerStage, a.Nd - j0);
+    __syncthreads();  // the previous stage has been consumed
+    if (t < nsb) {
+      const double4 s = sens[j0 + t];
+      const double dx = s.x - T.cx, dy = s.y - T.cy, dz = s.z - T.cz;
+      const double R = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
+      nbs[t] = (int)floor((R - T.rho) * a.inv_vdt - a.t0_over_dt - a.hmax) - 1;
+    }
+    __syncthreads();
+    for (int js = wave; js < nsb; js += BLOCK / kWave) {
+      const float *drow = a.delta + (int64_t)(j0 + js) * a.Nt;
+      const int nb = nbs[js];
+      for (int c = lane; c < a.L; c += kWave) {
+        const int n = nb + c;
+        stage[js * a.L + c] = (n >= 0 && n < a.Nt) ? drow[n] : 0.0f;
+      }
+    }
+    __syncthreads();
+
+    float sA = 0.0f, sN[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    for (int js = 0; js < nsb; ++js) {
+      AnisoPair p;
+      aniso_pair(sens[j0 + js], r, a.inv_vdt, a.t0_over_dt, a.nsig, a.smax2, p);
+      const int o = (int)(p.lo - nbs[js]);
+      const float *row = stage + js * a.L;
+      float s1 = 0.0f, s3 = 0.0f;
+      for (int i0 = 0; i0 < p.ntap; i0 += kTapRunAniso) {
+        float d = p.d0 - (float)i0;
+        float f = __builtin_amdgcn_exp2f(p.c * d * d);
+        float q = __builtin_amdgcn_exp2f(fmaf(p.k1, d, p.c));
+        const int iend = min(i0 + kTapRunAniso, p.ntap);
+        for (int ii = i0; ii < iend; ++ii) {
+          const float pd = row[min(max(o + ii, 0), Lm1)] * f * d;
+          s1 += pd;
+          if (SIGMA) s3 = fmaf(pd, d * d, s3);
+          d -= 1.0f;
+          f *= q;
+          q *= p.rq;
+        }
+      }
+      // W = sqrt(det) / sigma_n^3 * Delta / (2r): gA += W s1
+      const double W = (double)r.sq / (p.sn2 * sqrt(p.sn2)) * (a.vdt / (2.0 * p.r));
+      sA = fmaf((float)W, s1, sA);
+      if (SIGMA) {
+        // W / (2 sigma_n^2) (s3 / su2 - 3 s1) along n n^T, su2 = sigma_n^2 / Delta^2
+        const double su2 = p.sn2 * a.inv_vdt * a.inv_vdt;
+        const float G = (float)(W / (2.0 * p.sn2)) * (s3 / (float)su2 - 3.0f * s1);
+        const float nx = (float)(p.ux / p.r), ny = (float)(p.uy / p.r), nz = (float)(p.uz / p.r);
+        sN[0] = fmaf(G * nx, nx, sN[0]);
+        sN[1] = fmaf(G * ny, ny, sN[1]);
+        sN[2] = fmaf(G * nz, nz, sN[2]);
+        sN[3] = fmaf(G * nx, ny, sN[3]);
+        sN[4] = fmaf(G * nx, nz, sN[4]);
+        sN[5] = fmaf(G * ny, nz, sN[5]);
+      }
+    }
+    accA += (double)sA;
+    if (SIGMA) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) accN[c] += (double)sN[c];
+    }
+  }
+  if (!live) return;
+  const int32_t k = a.perm[i];
+  a.gA[k] = (float)accA;
+  if (SIGMA) {
+    const double xx = r.sxx, yy = r.syy, zz = r.szz, xy = r.sxy, xz = r.sxz, yz = r.syz;
+    const double det = xx * (yy * zz - yz * yz) - xy * (xy * zz - yz * xz) + xz * (xy * yz - yy * xz);
+    const double inv[6] = {(yy * zz - yz * yz) / det, (xx * zz - xz * xz) / det,
+                           (xx * yy - xy * xy) / det, (xz * yz - xy * zz) / det,
+                           (xy * yz - xz * yy) / det, (xy * xz - xx * yz) / det};
+    const double A = r.A, h = 0.5 * A * accA;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const double g = h * inv[c] + A * accN[c];
+      a.gS[(int64_t)c * a.M + k] = (float)(c < 3 ? g : 2.0 * g);
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_aniso_prep(const gpair_plan_s *p, const float *A, const float *sig6,
+                             hipStream_t s) {
+  const int64_t M = p->M;
+  const double smax = p->sigma_max * (1.0 + 1e-6);
+  aniso_prep_kernel<<<(unsigned int)((M + 255) / 256), 256, 0, s>>>(
+      A, sig6, ws_perm(p), (AnisoRec *)ws_krec(p), M, smax * smax, ws_counters(p));
+  return hipGetLastError();
+}
+
+hipError_t launch_aniso_forward(const gpair_plan_s *p, float *y, hipStream_t s) {
+  AnisoFwdArgs a;
+  a.sens = (const double4 *)ws_sens(p);
+  a.tiles = ws_ftiles(p);
+  a.y = y;
+  a.Nd = p->Nd;
+  a.Nt = p->Nt;
+  a.nsg = (p->Nd + kWave - 1) / kWave;
+  a.nlogical = (int64_t)p->host.ftiles.size() * a.nsg;
+  a.L = p->Lf;
+  a.inv_vdt = p->inv_vdt;
+  a.t0_over_dt = p->t0_over_dt;
+  a.hmax = p->hmax;
+  a.vdt = p->vdt;
+  a.nsig = p->nsig;
+  const double smax = p->sigma_max * (1.0 + 1e-6);
+  a.smax2 = smax * smax;
+  a.min_dist = p->min_dist;
+  const size_t lds = (size_t)p->Lf * kWave * sizeof(int);
+  aniso_forward_kernel<kAnisoWaves><<<xcd_grid_a(a.nlogical), kAnisoWaves * kWave, lds, s>>>(
+      (const AnisoRec *)ws_krec(p), a);
+  return hipGetLastError();
+}
+
+hipError_t launch_aniso_adjoint(const gpair_plan_s *p, const float *delta, float *gA,
+                                float *gsig6, hipStream_t s) {
+  AnisoAdjArgs a;
+  a.rec = (const AnisoRec *)ws_krec(p);
+  a.tiles = ws_atiles(p);
+  a.perm = ws_perm(p);
+  a.delta = delta;
+  a.gA = gA;
+  a.gS = gsig6;
+  a.nlogical = (int64_t)p->host.atiles.size();
+  a.M = p->M;
+  a.Nd = p->Nd;
+  a.Nt = p->Nt;
+  a.L = p->La;
+  a.inv_vdt = p->inv_vdt;
+  a.t0_over_dt = p->t0_over_dt;
+  a.hmax = p->hmax;
+  a.vdt = p->vdt;
+  a.nsig = p->nsig;
+  const double smax = p->sigma_max * (1.0 + 1e-6);
+  a.smax2 = smax * smax;
+  const size_t lds = (size_t)p->La * kAdjSensorsPerStage * sizeof(float);
+  const unsigned int grid = xcd_grid_a(a.nlogical);
+  const double4 *sens = (const double4 *)ws_sens(p);
+#define GPAIR_ANISO_ADJ(B)                                                                 \
+  if (gsig6)                                                                               \
+    aniso_adjoint_kernel<B, true><<<grid, B, lds, s>>>(sens, a);                           \
+  else                                                                                     \
+    aniso_adjoint_kernel<B, false><<<grid, B, lds, s>>>(sens, a);
+  switch (p->adj_tile) {
+    case 64: GPAIR_ANISO_ADJ(64) break;
+    case 128: GPAIR_ANISO_ADJ(128) break;
+    default: GPAIR_ANISO_ADJ(256) break;
+  }
+#undef GPAIR_ANISO_ADJ
+  return hipGetLastError();
+}
+
+}  // namespace gpair

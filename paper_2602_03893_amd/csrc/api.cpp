@@ -253,6 +253,35 @@ gpair_status gpair_adjoint_centres(gpair_plan p, const float *A, const float *si
   return adjoint_records(p, delta, gA, gsigma, gcentres, s);
 }
 
+gpair_status gpair_forward_aniso(gpair_plan p, const float *A, const float *sigma6, float *y,
+                                 gpair_stream stream) {
+  if (!bound(p) || !A || !sigma6 || !y) return GPAIR_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  p->prepared = 0;  // the anisotropic records overwrite the direct coefficients
+  hipError_t e = launch_aniso_prep(p, A, sigma6, s);
+  if (e == hipSuccess) e = launch_fill(y, (int64_t)p->Nd * p->Nt, 0.0f, s);
+  if (e != hipSuccess) return GPAIR_ERR_HIP;
+  timer_begin(p, GPAIR_TIMER_FORWARD, s);
+  e = launch_aniso_forward(p, y, s);
+  timer_end(p, GPAIR_TIMER_FORWARD, s);
+  return hip_status(e);
+}
+
+gpair_status gpair_adjoint_aniso(gpair_plan p, const float *A, const float *sigma6,
+                                 const float *delta, float *gA, float *gsigma6,
+                                 gpair_stream stream) {
+  if (!bound(p) || !sigma6 || !delta || !gA) return GPAIR_ERR_INVALID_ARG;
+  if (gsigma6 && !A) return GPAIR_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  p->prepared = 0;
+  hipError_t e = launch_aniso_prep(p, A, sigma6, s);
+  if (e != hipSuccess) return GPAIR_ERR_HIP;
+  timer_begin(p, GPAIR_TIMER_ADJOINT, s);
+  e = launch_aniso_adjoint(p, delta, gA, gsigma6, s);
+  timer_end(p, GPAIR_TIMER_ADJOINT, s);
+  return hip_status(e);
+}
+
 gpair_status gpair_assa_grid_params(gpair_plan p, double sigma, gpair_assa_grid *out) {
   if (!p || !out) return GPAIR_ERR_INVALID_ARG;
   AssaGrid g;

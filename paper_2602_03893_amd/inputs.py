@@ -275,3 +275,19 @@ def sensor_array(w: Workload):
 def geometry_arrays(w: Workload):
     """(centres (M,3) float32, sensors (N_d,3) float32) of a workload."""
     return grid_centres(*w.grid, w.spacing), sensor_array(w)
+
+
+def covariances(m, seed, lo, hi):
+    """Seeded anisotropic covariances, (6, m) float32 (rows xx, yy, zz, xy, xz,
+    yz, m^2): R diag(s1^2, s2^2, s3^2) R^T with axes s_i ~ U[lo, hi] and R a
+    uniformly random rotation (QR of a Gaussian matrix, sign-fixed).  Vectorised
+    over kernels; the entries are rounded to float32 once, and the operators
+    and the oracle both take those float32 values."""
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal((m, 3, 3))
+    q, r = np.linalg.qr(g)
+    q = q * np.sign(np.diagonal(r, axis1=1, axis2=2))[:, None, :]
+    s2 = rng.uniform(lo, hi, (m, 3)) ** 2
+    c = np.einsum("kij,kj,klj->kil", q, s2, q)
+    out = np.stack([c[:, 0, 0], c[:, 1, 1], c[:, 2, 2], c[:, 0, 1], c[:, 0, 2], c[:, 1, 2]])
+    return out.astype(np.float32)
