@@ -54,7 +54,6 @@ static_assert(offsetof(AnisoRec, fcz) == offsetof(KernelRec, fcz) &&
 
 constexpr int kAnisoWaves = 4;   // forward waves per workgroup
 constexpr int kTapRunAniso = 16; // taps between exact Gaussian factors
-constexpr double kLog2eA = 1.4426950408889634;
 
 __device__ __forceinline__ int64_t xcd_logical_a(int64_t nlogical) {
   const int64_t per = (nlogical + kXcds - 1) / kXcds;
@@ -116,45 +115,69 @@ __global__ __launch_bounds__(256) void aniso_prep_kernel(
   r.pk = (float)(fabs((double)a) * sq * tr * tr / (4.0 * det));
 }
 
-// One pair's window and tap constants.  u = s - c in float64; sigma_n^2 is
-// clamped to smax2 (the records admit no more; the clamp only absorbs
-// rounding), so the window never exceeds the plan's widest.
+// sqrt(x) and 1/(2 sqrt(x)) for a positive normal float64 x: the float64
+// reciprocal-square-root seed, one coupled Newton step on both and two
+// corrections of the root (the sequence the compiler uses for sqrt, without
+// its rescaling of tiny or huge inputs, which these distances never are).
+__device__ __forceinline__ double sqrt_and_half_rinv(double x, double &h) {
+  const double g = __builtin_amdgcn_rsq(x);
+  double sr = x * g;
+  h = 0.5 * g;
+  const double e = fma(-h, sr, 0.5);
+  sr = fma(sr, e, sr);
+  h = fma(h, e, h);
+  double d = fma(-sr, sr, x);
+  sr = fma(d, h, sr);
+  d = fma(-sr, sr, x);
+  return fma(d, h, sr);
+}
+
+// One pair's window (float64, as the definition) and its float32 tap
+// constants.  sigma_n^2 is clamped to smax2 (the records admit no more; the
+// clamp only absorbs rounding), so the window never exceeds the plan's widest.
 struct AnisoPair {
-  double ux, uy, uz, r2, r;
-  double sn2;      // sigma_n^2 (m^2)
-  int64_t lo;      // first in-window sample
+  int lo;          // first in-window sample
   int ntap;        // in-window samples (>= 0)
   float d0;        // offset of sample lo from the pulse centre, samples
-  float c, k1, rq; // exp2(c u^2) = exp(-d^2/(2 sigma_n^2)); ratio constants
+  float c, k1, rq; // exp2(c u^2) = exp(-d^2/(2 sigma_n^2)), u = d / Delta; ratio constants
+  float rinv;      // 1/r
+  float isn;       // 1/sigma_n (1/m)
+  float nx, ny, nz;  // n = (s - c)/r
 };
 
 __device__ __forceinline__ void aniso_pair(const double4 &s, const AnisoRec &k, double inv_vdt,
-                                           double t0_over_dt, double nsig, double smax2,
-                                           AnisoPair &p) {
-  p.ux = s.x - (double)k.fcx;
-  p.uy = s.y - (double)k.fcy;
-  p.uz = s.z - (double)k.fcz;
-  p.r2 = fma(p.uz, p.uz, fma(p.uy, p.uy, p.ux * p.ux));
-  p.r = sqrt(p.r2);
-  const double q = (double)k.sxx * p.ux * p.ux + (double)k.syy * p.uy * p.uy +
-                   (double)k.szz * p.uz * p.uz +
-                   2.0 * ((double)k.sxy * p.ux * p.uy + (double)k.sxz * p.ux * p.uz +
-                          (double)k.syz * p.uy * p.uz);
-  double sn2 = q / p.r2;
+                                           double t0_over_dt, double nsig_inv_vdt, float vdt_f,
+                                           double smax2, AnisoPair &p) {
+  const double ux = s.x - (double)k.fcx, uy = s.y - (double)k.fcy, uz = s.z - (double)k.fcz;
+  const double r2 = fma(uz, uz, fma(uy, uy, ux * ux));
+  double hr;
+  const double r = sqrt_and_half_rinv(r2, hr);
+  const double rinv = 2.0 * hr;
+  const double q = fma((double)k.sxx * ux, ux,
+                   fma((double)k.syy * uy, uy,
+                   fma((double)k.szz * uz, uz,
+                       2.0 * fma((double)k.sxy * ux, uy,
+                             fma((double)k.sxz * ux, uz, (double)k.syz * uy * uz)))));
+  double sn2 = q * rinv * rinv;
   sn2 = (sn2 > 0.0 && sn2 <= smax2) ? sn2 : smax2;
-  p.sn2 = sn2;
-  const double hs = nsig * sqrt(sn2) * inv_vdt;
-  const double nc = fma(p.r, inv_vdt, -t0_over_dt);
+  double hs_;
+  const double sn = sqrt_and_half_rinv(sn2, hs_);
+  const double hs = nsig_inv_vdt * sn;
+  const double nc = fma(r, inv_vdt, -t0_over_dt);
   const double lo = ceil(nc - hs);
   const double hi = floor(nc + hs);
-  p.lo = (int64_t)lo;
+  p.lo = (int)lo;
   p.ntap = hi >= lo ? (int)(hi - lo) + 1 : 0;
   p.d0 = (float)(nc - lo);
-  const double su2 = sn2 * inv_vdt * inv_vdt;  // sigma_n^2 in samples^2
-  const double c = -kLog2eA / (2.0 * su2);
-  p.c = (float)c;
-  p.k1 = (float)(-2.0 * c);
-  p.rq = (float)exp2(2.0 * c);
+  p.rinv = (float)rinv;
+  p.isn = (float)(2.0 * hs_);
+  const float iu = vdt_f * p.isn;  // Delta / sigma_n
+  p.c = -0.72134752044448170f * iu * iu;  // -log2(e)/2 (Delta/sigma_n)^2
+  p.k1 = -2.0f * p.c;
+  p.rq = __builtin_amdgcn_exp2f(2.0f * p.c);
+  p.nx = (float)(ux * rinv);
+  p.ny = (float)(uy * rinv);
+  p.nz = (float)(uz * rinv);
 }
 
 // ---------------------------------------------------------------------------
@@ -210,32 +233,34 @@ __global__ __launch_bounds__(WAVES * kWave) void aniso_forward_kernel(
   const double iuw = bound > 0.0 ? 0x1p30 / bound : 0.0;
   __syncthreads();
 
-  // Slots: o = lo - nb >= 1 and o + ntap - 1 <= L - 1 for every pair (the
+  // Slots: lo - nb >= 1 and lo - nb + ntap - 1 <= L - 1 for every pair (the
   // plan's slot bound with the widest admitted window, which no sigma_n
-  // exceeds); the clamps keep the masked taps past a short window, which the
-  // wave runs up to its longest, inside the segment.
+  // exceeds); a lane adds only its own window's taps while the wave runs to
+  // its longest.
   int *const col = seg + lane;
-  const int Lm1 = a.L - 1;
+  const float wsc = (float)(0.5 * a.vdt * iuw);  // Delta/2 in fixed-point units
+  const float vdt_f = (float)a.vdt;
+  const double nsig_inv_vdt = a.nsig * a.inv_vdt;
   for (int k = T.start + wave; k < T.start + T.count; k += WAVES) {
     const AnisoRec r = rec[k];
     AnisoPair p;
-    aniso_pair(s, r, a.inv_vdt, a.t0_over_dt, a.nsig, a.smax2, p);
+    aniso_pair(s, r, a.inv_vdt, a.t0_over_dt, nsig_inv_vdt, vdt_f, a.smax2, p);
     // p = A sq / sigma_n^3 * (u Delta) / (2r) * exp2(c u^2), u in samples
-    const double w = (double)r.A * (double)r.sq / (p.sn2 * sqrt(p.sn2)) * (a.vdt / (2.0 * p.r)) * iuw;
-    const int o = (int)(p.lo - nb);
+    const float w = r.A * r.sq * (p.isn * p.isn * p.isn) * wsc * p.rinv;
+    int *const pa = col + (p.lo - nb) * kWave;
     const int n = p.ntap;
     int nmax = n;
     for (int off = 32; off > 0; off >>= 1) nmax = max(nmax, __shfl_xor(nmax, off, kWave));
     for (int i0 = 0; i0 < nmax; i0 += kTapRunAniso) {
-      float d = p.d0 - (float)i0;
-      float f = (float)w * __builtin_amdgcn_exp2f(p.c * d * d);
+      const float d = p.d0 - (float)i0;
+      float f = w * __builtin_amdgcn_exp2f(p.c * d * d);
       float q = __builtin_amdgcn_exp2f(fmaf(p.k1, d, p.c));
+      float tv = f * d;  // t_i = f_i u_i; t_{i+1} = q_i t_i - f_{i+1}
       const int iend = min(i0 + kTapRunAniso, nmax);
       for (int i = i0; i < iend; ++i) {
-        const float v = i < n ? f * d : 0.0f;
-        lds_add_fx(col + min(max(o + i, 0), Lm1) * kWave, v);
-        d -= 1.0f;
+        if (i < n) lds_add_fx(pa + i * kWave, tv);
         f *= q;
+        tv = fmaf(q, tv, -f);
         q *= p.rq;
       }
     }
@@ -292,7 +317,8 @@ __global__ __launch_bounds__(BLOCK) void aniso_adjoint_kernel(const double4 *__r
   const bool live = t < T.count;
   const int64_t i = T.start + (live ? t : 0);
   const AnisoRec r = a.rec[i];
-  const int Lm1 = a.L - 1;
+  const float vdt_f = (float)a.vdt, hvdt = 0.5f * (float)a.vdt;
+  const double nsig_inv_vdt = a.nsig * a.inv_vdt;
 
   double accA = 0.0, accN[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int j0 = 0; j0 < a.Nd; j0 += kAdjSensorsPerStage) {
@@ -318,9 +344,8 @@ __global__ __launch_bounds__(BLOCK) void aniso_adjoint_kernel(const double4 *__r
     float sA = 0.0f, sN[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     for (int js = 0; js < nsb; ++js) {
       AnisoPair p;
-      aniso_pair(sens[j0 + js], r, a.inv_vdt, a.t0_over_dt, a.nsig, a.smax2, p);
-      const int o = (int)(p.lo - nbs[js]);
-      const float *row = stage + js * a.L;
+      aniso_pair(sens[j0 + js], r, a.inv_vdt, a.t0_over_dt, nsig_inv_vdt, vdt_f, a.smax2, p);
+      const float *rp = stage + js * a.L + (p.lo - nbs[js]);
       float s1 = 0.0f, s3 = 0.0f;
       for (int i0 = 0; i0 < p.ntap; i0 += kTapRunAniso) {
         float d = p.d0 - (float)i0;
@@ -328,7 +353,7 @@ __global__ __launch_bounds__(BLOCK) void aniso_adjoint_kernel(const double4 *__r
         float q = __builtin_amdgcn_exp2f(fmaf(p.k1, d, p.c));
         const int iend = min(i0 + kTapRunAniso, p.ntap);
         for (int ii = i0; ii < iend; ++ii) {
-          const float pd = row[min(max(o + ii, 0), Lm1)] * f * d;
+          const float pd = rp[ii] * f * d;
           s1 += pd;
           if (SIGMA) s3 = fmaf(pd, d * d, s3);
           d -= 1.0f;
@@ -337,19 +362,18 @@ __global__ __launch_bounds__(BLOCK) void aniso_adjoint_kernel(const double4 *__r
         }
       }
       // W = sqrt(det) / sigma_n^3 * Delta / (2r): gA += W s1
-      const double W = (double)r.sq / (p.sn2 * sqrt(p.sn2)) * (a.vdt / (2.0 * p.r));
-      sA = fmaf((float)W, s1, sA);
+      const float W = r.sq * (p.isn * p.isn * p.isn) * hvdt * p.rinv;
+      sA = fmaf(W, s1, sA);
       if (SIGMA) {
-        // W / (2 sigma_n^2) (s3 / su2 - 3 s1) along n n^T, su2 = sigma_n^2 / Delta^2
-        const double su2 = p.sn2 * a.inv_vdt * a.inv_vdt;
-        const float G = (float)(W / (2.0 * p.sn2)) * (s3 / (float)su2 - 3.0f * s1);
-        const float nx = (float)(p.ux / p.r), ny = (float)(p.uy / p.r), nz = (float)(p.uz / p.r);
-        sN[0] = fmaf(G * nx, nx, sN[0]);
-        sN[1] = fmaf(G * ny, ny, sN[1]);
-        sN[2] = fmaf(G * nz, nz, sN[2]);
-        sN[3] = fmaf(G * nx, ny, sN[3]);
-        sN[4] = fmaf(G * nx, nz, sN[4]);
-        sN[5] = fmaf(G * ny, nz, sN[5]);
+        // W / (2 sigma_n^2) (s3 (Delta/sigma_n)^2 - 3 s1) along n n^T
+        const float iu = vdt_f * p.isn;
+        const float G = W * 0.5f * (p.isn * p.isn) * fmaf(s3, iu * iu, -3.0f * s1);
+        sN[0] = fmaf(G * p.nx, p.nx, sN[0]);
+        sN[1] = fmaf(G * p.ny, p.ny, sN[1]);
+        sN[2] = fmaf(G * p.nz, p.nz, sN[2]);
+        sN[3] = fmaf(G * p.nx, p.ny, sN[3]);
+        sN[4] = fmaf(G * p.nx, p.nz, sN[4]);
+        sN[5] = fmaf(G * p.ny, p.nz, sN[5]);
       }
     }
     accA += (double)sA;
