@@ -29,6 +29,7 @@
 // matrix entry).
 #include <cmath>
 
+#include "filter.h"
 #include "gpair_internal.h"
 
 namespace gpair {
@@ -132,22 +133,41 @@ __device__ __forceinline__ double sqrt_and_half_rinv(double x, double &h) {
   return fma(d, h, sr);
 }
 
-// One pair's window (float64, as the definition) and its float32 tap
-// constants.  sigma_n^2 is clamped to smax2 (the records admit no more; the
-// clamp only absorbs rounding), so the window never exceeds the plan's widest.
+// One pair's window (slot of its first sample relative to the segment base,
+// sample count, offset of that sample from the pulse centre) and its float32
+// tap constants.
 struct AnisoPair {
-  int lo;          // first in-window sample
+  int o;           // first in-window sample minus the segment base nb
   int ntap;        // in-window samples (>= 0)
-  float d0;        // offset of sample lo from the pulse centre, samples
-  float c, k1, rq; // exp2(c u^2) = exp(-d^2/(2 sigma_n^2)), u = d / Delta; ratio constants
+  float d0;        // offset of sample o from the pulse centre, samples
   float rinv;      // 1/r
   float isn;       // 1/sigma_n (1/m)
-  float nx, ny, nz;  // n = (s - c)/r
+  float nx, ny, nz;  // n = (s - c)/r (adjoint only)
 };
 
-__device__ __forceinline__ void aniso_pair(const double4 &s, const AnisoRec &k, double inv_vdt,
-                                           double t0_over_dt, double nsig_inv_vdt, float vdt_f,
-                                           double smax2, AnisoPair &p) {
+// exp2(c u^2) = exp(-d^2/(2 sigma_n^2)) for u = d / Delta; the ratio of
+// consecutive taps is exp2(k1 u + c), itself multiplied by rq each tap.
+struct AnisoGauss {
+  float c, k1, rq;
+};
+
+__device__ __forceinline__ AnisoGauss aniso_gauss(float isn, float vdt_f) {
+  AnisoGauss g;
+  const float iu = vdt_f * isn;  // Delta / sigma_n
+  g.c = -0.72134752044448170f * iu * iu;  // -log2(e)/2 (Delta/sigma_n)^2
+  g.k1 = -2.0f * g.c;
+  g.rq = __builtin_amdgcn_exp2f(2.0f * g.c);
+  return g;
+}
+
+// The float64 decision, as the definition: u = s - c from the caller's
+// float32 centre, r, sigma_n^2 = u^T Sigma u / r^2 (clamped to smax2: the
+// records admit no more, the clamp only absorbs rounding, so no window
+// exceeds the plan's widest), the first and last sample with
+// |r - v t| <= n_sigma sigma_n.
+__device__ __forceinline__ void aniso_exact(const double4 &s, const AnisoRec &k, int nb,
+                                            double inv_vdt, double t0_over_dt,
+                                            double nsig_inv_vdt, double smax2, AnisoPair &p) {
   const double ux = s.x - (double)k.fcx, uy = s.y - (double)k.fcy, uz = s.z - (double)k.fcz;
   const double r2 = fma(uz, uz, fma(uy, uy, ux * ux));
   double hr;
@@ -166,18 +186,55 @@ __device__ __forceinline__ void aniso_pair(const double4 &s, const AnisoRec &k, 
   const double nc = fma(r, inv_vdt, -t0_over_dt);
   const double lo = ceil(nc - hs);
   const double hi = floor(nc + hs);
-  p.lo = (int)lo;
+  p.o = (int)lo - nb;
   p.ntap = hi >= lo ? (int)(hi - lo) + 1 : 0;
   p.d0 = (float)(nc - lo);
   p.rinv = (float)rinv;
   p.isn = (float)(2.0 * hs_);
-  const float iu = vdt_f * p.isn;  // Delta / sigma_n
-  p.c = -0.72134752044448170f * iu * iu;  // -log2(e)/2 (Delta/sigma_n)^2
-  p.k1 = -2.0f * p.c;
-  p.rq = __builtin_amdgcn_exp2f(2.0f * p.c);
   p.nx = (float)(ux * rinv);
   p.ny = (float)(uy * rinv);
   p.nz = (float)(uz * rinv);
+}
+
+// The float32 filter from the block's constants (filter.h): dr = r - R by
+// the block's fixed-point steps as in the isotropic operators, u = s - c_k =
+// (s - c_B) - dk, sigma_n from u^T Sigma u and 1/r, then both window ends
+// z -+ h_n about the pulse centre z (samples past Xi).  Returns true when an
+// end lies within kGuard of a sample (then the caller decides with
+// aniso_exact).  Its error is the isotropic filter's in z (below kGuard / 2 by
+// the planner's bound) plus about ten float32 units of h_n from sigma_n, so a
+// decision outside the guard equals the float64 one.
+__device__ __forceinline__ bool aniso_filter(const BlockLane &bl, int kit, const AnisoRec &k,
+                                             float nsig_inv_vdt, float inv_vdt_f, float smax2f,
+                                             AnisoPair &p) {
+  const float D = fmaf(bl.m2ux, k.dx, fmaf(bl.m2uy, k.dy, fmaf(bl.m2uz, k.dz, k.dd)));
+  float dr = D * bl.inv2R;
+  for (int it = 0; it < kit; ++it) dr = fmaf(-dr, dr, D) * bl.inv2R;
+  const float ux = fmaf(-0.5f, bl.m2ux, -k.dx);
+  const float uy = fmaf(-0.5f, bl.m2uy, -k.dy);
+  const float uz = fmaf(-0.5f, bl.m2uz, -k.dz);
+  const float q = fmaf(k.sxx * ux, ux,
+                  fmaf(k.syy * uy, uy,
+                  fmaf(k.szz * uz, uz,
+                       2.0f * fmaf(k.sxy * ux, uy, fmaf(k.sxz * ux, uz, k.syz * uy * uz)))));
+  const float rinv = __builtin_amdgcn_rcpf(bl.Rf + dr);
+  float sn2 = q * rinv * rinv;
+  sn2 = (sn2 > 0.0f && sn2 <= smax2f) ? sn2 : smax2f;
+  const float isn = __builtin_amdgcn_rsqf(sn2);
+  const float hs = nsig_inv_vdt * (sn2 * isn);
+  const float zc = fmaf(dr, inv_vdt_f, bl.Xf);
+  const float zl = zc - hs, zh = zc + hs;
+  const float cl = ceilf(zl), fh = floorf(zh);
+  p.o = bl.Xi + (int)cl;
+  p.ntap = fh >= cl ? (int)(fh - cl) + 1 : 0;
+  p.d0 = zc - cl;
+  p.rinv = rinv;
+  p.isn = isn;
+  p.nx = ux * rinv;
+  p.ny = uy * rinv;
+  p.nz = uz * rinv;
+  const float m = fminf(fminf(cl - zl, zl + 1.0f - cl), fminf(zh - fh, fh + 1.0f - zh));
+  return m < kGuard;
 }
 
 // ---------------------------------------------------------------------------
@@ -186,8 +243,10 @@ __device__ __forceinline__ void aniso_pair(const double4 &s, const AnisoRec &k, 
 struct AnisoFwdArgs {
   const double4 *sens;
   const TileInfo *tiles;
+  const TileInfo *blocks;  // adjoint tiles: the filter's reference blocks
   float *y;
   int64_t nlogical;
+  int32_t ntiles, nblocks;
   int32_t Nd, Nt, nsg, L;
   double inv_vdt, t0_over_dt, hmax, vdt, nsig, smax2, min_dist;
 };
@@ -233,35 +292,46 @@ __global__ __launch_bounds__(WAVES * kWave) void aniso_forward_kernel(
   const double iuw = bound > 0.0 ? 0x1p30 / bound : 0.0;
   __syncthreads();
 
-  // Slots: lo - nb >= 1 and lo - nb + ntap - 1 <= L - 1 for every pair (the
-  // plan's slot bound with the widest admitted window, which no sigma_n
-  // exceeds); a lane adds only its own window's taps while the wave runs to
-  // its longest.
+  // Slots: o >= 1 and o + ntap - 1 <= L - 1 for every pair (the plan's slot
+  // bound with the widest admitted window, which no sigma_n exceeds); a lane
+  // adds only its own window's taps while the wave runs to its longest.
   int *const col = seg + lane;
   const float wsc = (float)(0.5 * a.vdt * iuw);  // Delta/2 in fixed-point units
-  const float vdt_f = (float)a.vdt;
+  const float vdt_f = (float)a.vdt, inv_vdt_f = (float)a.inv_vdt;
   const double nsig_inv_vdt = a.nsig * a.inv_vdt;
-  for (int k = T.start + wave; k < T.start + T.count; k += WAVES) {
-    const AnisoRec r = rec[k];
-    AnisoPair p;
-    aniso_pair(s, r, a.inv_vdt, a.t0_over_dt, nsig_inv_vdt, vdt_f, a.smax2, p);
-    // p = A sq / sigma_n^3 * (u Delta) / (2r) * exp2(c u^2), u in samples
-    const float w = r.A * r.sq * (p.isn * p.isn * p.isn) * wsc * p.rinv;
-    int *const pa = col + (p.lo - nb) * kWave;
-    const int n = p.ntap;
-    int nmax = n;
-    for (int off = 32; off > 0; off >>= 1) nmax = max(nmax, __shfl_xor(nmax, off, kWave));
-    for (int i0 = 0; i0 < nmax; i0 += kTapRunAniso) {
-      const float d = p.d0 - (float)i0;
-      float f = w * __builtin_amdgcn_exp2f(p.c * d * d);
-      float q = __builtin_amdgcn_exp2f(fmaf(p.k1, d, p.c));
-      float tv = f * d;  // t_i = f_i u_i; t_{i+1} = q_i t_i - f_{i+1}
-      const int iend = min(i0 + kTapRunAniso, nmax);
-      for (int i = i0; i < iend; ++i) {
-        if (i < n) lds_add_fx(pa + i * kWave, tv);
-        f *= q;
-        tv = fmaf(q, tv, -f);
-        q *= p.rq;
+  const float nsig_inv_vdt_f = (float)nsig_inv_vdt, smax2f = (float)a.smax2;
+  // The waves take the tile's reference blocks (the adjoint tiles nested in
+  // it) in turn; each sets up its block's filter constants per lane.
+  const int bend = tile + 1 < a.ntiles ? a.tiles[tile + 1].first_block : a.nblocks;
+  for (int b = T.first_block + wave; b < bend; b += WAVES) {
+    const TileInfo B = a.blocks[b];
+    BlockLane bl;
+    block_lane(s, B, nb, a.inv_vdt, a.t0_over_dt, bl);
+    const int kit = B.filter_steps;
+    for (int k = B.start; k < B.start + B.count; ++k) {
+      const AnisoRec r = rec[k];
+      AnisoPair p;
+      if (kit < 0 || aniso_filter(bl, kit, r, nsig_inv_vdt_f, inv_vdt_f, smax2f, p))
+        aniso_exact(s, r, nb, a.inv_vdt, a.t0_over_dt, nsig_inv_vdt, a.smax2, p);
+      const AnisoGauss gs = aniso_gauss(p.isn, vdt_f);
+      // p = A sq / sigma_n^3 * (u Delta) / (2r) * exp2(c u^2), u in samples
+      const float w = r.A * r.sq * (p.isn * p.isn * p.isn) * wsc * p.rinv;
+      int *const pa = col + p.o * kWave;
+      const int n = p.ntap;
+      int nmax = n;
+      for (int off = 32; off > 0; off >>= 1) nmax = max(nmax, __shfl_xor(nmax, off, kWave));
+      for (int i0 = 0; i0 < nmax; i0 += kTapRunAniso) {
+        const float d = p.d0 - (float)i0;
+        float f = w * __builtin_amdgcn_exp2f(gs.c * d * d);
+        float q = __builtin_amdgcn_exp2f(fmaf(gs.k1, d, gs.c));
+        float tv = f * d;  // t_i = f_i u_i; t_{i+1} = q_i t_i - f_{i+1}
+        const int iend = min(i0 + kTapRunAniso, nmax);
+        for (int i = i0; i < iend; ++i) {
+          if (i < n) lds_add_fx(pa + i * kWave, tv);
+          f *= q;
+          tv = fmaf(q, tv, -f);
+          q *= gs.rq;
+        }
       }
     }
   }
@@ -307,6 +377,8 @@ __global__ __launch_bounds__(BLOCK) void aniso_adjoint_kernel(const double4 *__r
                                                               AnisoAdjArgs a) {
   extern __shared__ float stage[];  // [kAdjSensorsPerStage][L]
   __shared__ int nbs[kAdjSensorsPerStage];
+  __shared__ float4 su[kAdjSensorsPerStage];  // -2u (x, y, z), 1/(2R)
+  __shared__ float4 sv[kAdjSensorsPerStage];  // R, Xf, Xi (bits), unused
 
   const int64_t logical = xcd_logical_a(a.nlogical);
   if (logical >= a.nlogical) return;
@@ -317,8 +389,10 @@ __global__ __launch_bounds__(BLOCK) void aniso_adjoint_kernel(const double4 *__r
   const bool live = t < T.count;
   const int64_t i = T.start + (live ? t : 0);
   const AnisoRec r = a.rec[i];
-  const float vdt_f = (float)a.vdt, hvdt = 0.5f * (float)a.vdt;
+  const int kit = T.filter_steps;
+  const float vdt_f = (float)a.vdt, hvdt = 0.5f * (float)a.vdt, inv_vdt_f = (float)a.inv_vdt;
   const double nsig_inv_vdt = a.nsig * a.inv_vdt;
+  const float nsig_inv_vdt_f = (float)nsig_inv_vdt, smax2f = (float)a.smax2;
 
   double accA = 0.0, accN[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int j0 = 0; j0 < a.Nd; j0 += kAdjSensorsPerStage) {
@@ -328,7 +402,12 @@ __global__ __launch_bounds__(BLOCK) void aniso_adjoint_kernel(const double4 *__r
       const double4 s = sens[j0 + t];
       const double dx = s.x - T.cx, dy = s.y - T.cy, dz = s.z - T.cz;
       const double R = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
-      nbs[t] = (int)floor((R - T.rho) * a.inv_vdt - a.t0_over_dt - a.hmax) - 1;
+      const int nb = (int)floor((R - T.rho) * a.inv_vdt - a.t0_over_dt - a.hmax) - 1;
+      nbs[t] = nb;
+      BlockLane bl;
+      block_lane(s, T, nb, a.inv_vdt, a.t0_over_dt, bl);
+      su[t] = make_float4(bl.m2ux, bl.m2uy, bl.m2uz, bl.inv2R);
+      sv[t] = make_float4(bl.Rf, bl.Xf, __int_as_float(bl.Xi), 0.0f);
     }
     __syncthreads();
     for (int js = wave; js < nsb; js += BLOCK / kWave) {
@@ -344,13 +423,29 @@ __global__ __launch_bounds__(BLOCK) void aniso_adjoint_kernel(const double4 *__r
     float sA = 0.0f, sN[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     for (int js = 0; js < nsb; ++js) {
       AnisoPair p;
-      aniso_pair(sens[j0 + js], r, a.inv_vdt, a.t0_over_dt, nsig_inv_vdt, vdt_f, a.smax2, p);
-      const float *rp = stage + js * a.L + (p.lo - nbs[js]);
+      bool exact = kit < 0;
+      if (!exact) {
+        const float4 U = su[js];
+        const float4 V = sv[js];
+        BlockLane bl;
+        bl.m2ux = U.x;
+        bl.m2uy = U.y;
+        bl.m2uz = U.z;
+        bl.inv2R = U.w;
+        bl.Rf = V.x;
+        bl.Xf = V.y;
+        bl.Xi = __float_as_int(V.z);
+        exact = aniso_filter(bl, kit, r, nsig_inv_vdt_f, inv_vdt_f, smax2f, p);
+      }
+      if (exact)
+        aniso_exact(sens[j0 + js], r, nbs[js], a.inv_vdt, a.t0_over_dt, nsig_inv_vdt, a.smax2, p);
+      const AnisoGauss gs = aniso_gauss(p.isn, vdt_f);
+      const float *rp = stage + js * a.L + p.o;
       float s1 = 0.0f, s3 = 0.0f;
       for (int i0 = 0; i0 < p.ntap; i0 += kTapRunAniso) {
         float d = p.d0 - (float)i0;
-        float f = __builtin_amdgcn_exp2f(p.c * d * d);
-        float q = __builtin_amdgcn_exp2f(fmaf(p.k1, d, p.c));
+        float f = __builtin_amdgcn_exp2f(gs.c * d * d);
+        float q = __builtin_amdgcn_exp2f(fmaf(gs.k1, d, gs.c));
         const int iend = min(i0 + kTapRunAniso, p.ntap);
         for (int ii = i0; ii < iend; ++ii) {
           const float pd = rp[ii] * f * d;
@@ -358,7 +453,7 @@ __global__ __launch_bounds__(BLOCK) void aniso_adjoint_kernel(const double4 *__r
           if (SIGMA) s3 = fmaf(pd, d * d, s3);
           d -= 1.0f;
           f *= q;
-          q *= p.rq;
+          q *= gs.rq;
         }
       }
       // W = sqrt(det) / sigma_n^3 * Delta / (2r): gA += W s1
@@ -415,7 +510,10 @@ hipError_t launch_aniso_forward(const gpair_plan_s *p, float *y, hipStream_t s) 
   AnisoFwdArgs a;
   a.sens = (const double4 *)ws_sens(p);
   a.tiles = ws_ftiles(p);
+  a.blocks = ws_atiles(p);
   a.y = y;
+  a.ntiles = (int32_t)p->host.ftiles.size();
+  a.nblocks = (int32_t)p->host.atiles.size();
   a.Nd = p->Nd;
   a.Nt = p->Nt;
   a.nsg = (p->Nd + kWave - 1) / kWave;

@@ -51,16 +51,13 @@
 //    matching residual rows).
 #include <climits>
 
+#include "filter.h"
 #include "gpair_internal.h"
 
 namespace gpair {
 namespace {
 
 constexpr double kLog2e = 1.4426950408889634074;
-
-// Guard of the float32 window filter (samples): the planner admits a block
-// to the filter only when the filter's error bound is below kGuard / 2.
-constexpr float kGuard = (float)kFilterGuard;
 
 __device__ __forceinline__ int64_t xcd_logical_block(int64_t nlogical) {
   const int64_t per = (nlogical + kXcds - 1) / kXcds;
@@ -116,36 +113,6 @@ __global__ __launch_bounds__(256) void prep_kernel(
 // ---------------------------------------------------------------------------
 // Pair stage shared by both operators.
 // ---------------------------------------------------------------------------
-// Constants of the float32 filter for one (reference block, sensor).
-struct BlockLane {
-  float m2ux, m2uy, m2uz;  // -2 (s - c_B)
-  float inv2R;             // 1 / (2R)
-  float Rf;                // R
-  float Xf;                // X - Xi, X = R/(v dt) - t0/dt - nb
-  int Xi;                  // floor(X)
-};
-
-// Fills bl for the sensor at s (double4: x, y, z, |s|^2) and the block B
-// (its float32-rounded centre is the reference point).  The number of
-// fixed-point steps, or -1 (every pair in float64), is the block's
-// filter_steps, set by the planner from its closest sensor so that the
-// forward and the adjoint run the same arithmetic for every pair.
-__device__ __forceinline__ void block_lane(const double4 &s, const TileInfo &B, int nb,
-                                           double inv_vdt, double t0_over_dt, BlockLane &bl) {
-  const float bx = (float)B.cx, by = (float)B.cy, bz = (float)B.cz;
-  const double ux = s.x - (double)bx, uy = s.y - (double)by, uz = s.z - (double)bz;
-  const double R = sqrt(fma(uz, uz, fma(uy, uy, ux * ux)));
-  const double X = fma(R, inv_vdt, -t0_over_dt) - (double)nb;
-  const double Xi = floor(X);
-  bl.m2ux = (float)(-2.0 * ux);
-  bl.m2uy = (float)(-2.0 * uy);
-  bl.m2uz = (float)(-2.0 * uz);
-  bl.inv2R = (float)(0.5 / R);
-  bl.Rf = (float)R;
-  bl.Xf = (float)(X - Xi);
-  bl.Xi = (int)Xi;
-}
-
 // One pair's window: first tap's slot o (relative to the segment base nb),
 // offset d0 of the first tap from the pulse centre (samples, in (h-1, h]),
 // whether tap ntap-1 is in the window, and 1/r.
