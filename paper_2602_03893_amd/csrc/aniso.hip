@@ -257,6 +257,23 @@ __device__ __forceinline__ void lds_add_fx(int *p, float v) {
   __hip_atomic_fetch_add(p, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// The taps of one pair when the wave's longest window has NT samples (fully
+// unrolled, compile-time LDS offsets): t_i = f_i u_i by the fused
+// recurrence t_{i+1} = q_i t_i - f_{i+1}; the lane adds only its own n.
+template <int NT>
+__device__ __forceinline__ void aniso_taps(int *pa, float f, float q, float d, float rq, int n) {
+  float tv = f * d;
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    if (i < n) lds_add_fx(pa + i * kWave, tv);
+    if (i + 1 < NT) {
+      f *= q;
+      tv = fmaf(q, tv, -f);
+      q *= rq;
+    }
+  }
+}
+
 template <int WAVES>
 __global__ __launch_bounds__(WAVES * kWave) void aniso_forward_kernel(
     const AnisoRec *__restrict__ rec, AnisoFwdArgs a) {
@@ -320,6 +337,23 @@ __global__ __launch_bounds__(WAVES * kWave) void aniso_forward_kernel(
       const int n = p.ntap;
       int nmax = n;
       for (int off = 32; off > 0; off >>= 1) nmax = max(nmax, __shfl_xor(nmax, off, kWave));
+      nmax = __builtin_amdgcn_readfirstlane(nmax);
+      if (nmax <= 18) {
+        const float f0 = w * __builtin_amdgcn_exp2f(gs.c * p.d0 * p.d0);
+        const float q0 = __builtin_amdgcn_exp2f(fmaf(gs.k1, p.d0, gs.c));
+        switch (nmax) {
+#define GPAIR_ANISO_TAPS(k) \
+  case k: aniso_taps<k>(pa, f0, q0, p.d0, gs.rq, n); break;
+          GPAIR_ANISO_TAPS(1) GPAIR_ANISO_TAPS(2) GPAIR_ANISO_TAPS(3) GPAIR_ANISO_TAPS(4)
+          GPAIR_ANISO_TAPS(5) GPAIR_ANISO_TAPS(6) GPAIR_ANISO_TAPS(7) GPAIR_ANISO_TAPS(8)
+          GPAIR_ANISO_TAPS(9) GPAIR_ANISO_TAPS(10) GPAIR_ANISO_TAPS(11) GPAIR_ANISO_TAPS(12)
+          GPAIR_ANISO_TAPS(13) GPAIR_ANISO_TAPS(14) GPAIR_ANISO_TAPS(15) GPAIR_ANISO_TAPS(16)
+          GPAIR_ANISO_TAPS(17) GPAIR_ANISO_TAPS(18)
+#undef GPAIR_ANISO_TAPS
+          default: break;
+        }
+        continue;
+      }
       for (int i0 = 0; i0 < nmax; i0 += kTapRunAniso) {
         const float d = p.d0 - (float)i0;
         float f = w * __builtin_amdgcn_exp2f(gs.c * d * d);
