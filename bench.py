@@ -53,7 +53,9 @@ MEASURED_TRAFFIC = {
 
 
 # The same for the anisotropic kernels (aniso.hip).
-MEASURED_TRAFFIC_ANISO = {}
+MEASURED_TRAFFIC_ANISO = {
+    "d8de24d073bd331f": {"aniso_forward_kernel": 2.263e9, "aniso_adjoint_kernel": 0.919e9},
+}
 
 # The same for the ASSA kernels (assa.hip).
 MEASURED_TRAFFIC_ASSA = {
@@ -535,6 +537,72 @@ def bench_aniso(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_centres(args):
+    """Paper-scale IR step whose adjoint also returns the gradient with
+    respect to every kernel centre (gpair_adjoint_centres, learnable
+    centres): forward -> residual -> adjoint (A, sigma, centres) -> Adam on A
+    and sigma; the centres stay where the plan put them (moving them means
+    re-planning)."""
+    import numpy as np
+    import torch
+    from paper_2602_03893_amd import Plan, adam_update, inputs as I
+
+    w = I.WORKLOADS[args.workload]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    centres, sensors = I.geometry_arrays(w)
+    plan = Plan(centres, sensors, w.n_samples, w.dt, w.c_sound, n_sigma=w.n_sigma,
+                sigma_max=w.smax, device=dev)
+    M, Nd, Nt = w.n_kernels, w.n_sensors, w.n_samples
+    A_true = torch.tensor(I.phantom(w), device=dev)
+    sig0 = w.sigma
+    b = plan.forward(A_true, torch.full((M,), sig0, dtype=torch.float32, device=dev)).clone()
+    A = torch.zeros(M, dtype=torch.float32, device=dev)
+    sigma = torch.full((M,), sig0, dtype=torch.float32, device=dev)
+    mA, vA, mS, vS = (torch.zeros_like(A) for _ in range(4))
+    y = torch.empty((Nd, Nt), dtype=torch.float32, device=dev)
+    scale = 1.0 / float(torch.sum(b.double() ** 2))
+    state = {"t": 0}
+
+    def step():
+        state["t"] += 1
+        plan.forward(A, sigma, out=y)
+        plan.residual(y, b, scale=scale, delta=y)
+        gA, gS, _ = plan.adjoint_centres(A, sigma, y, want_sigma=True)
+        adam_update(A, gA, mA, vA, state["t"], 1e-2, lo=0.0)
+        adam_update(sigma, gS, mS, vS, state["t"], 1e-3 * sig0, lo=0.5 * sig0, hi=w.smax)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    f_ms = float(np.mean(plan.kernel_times("forward")))
+    a_ms = float(np.mean(plan.kernel_times("adjoint")))
+    plan.set_timing(False)
+    ms_step = 1e3 * elapsed / args.steps
+    value = 2.0 * float(M) * Nd * args.steps / elapsed / 1e9
+    log(f"bench --centres: {ms_step:.2f} ms/step, forward kernel {f_ms:.2f} ms, adjoint kernel "
+        f"(A, sigma, centres) {a_ms:.2f} ms, {value:.1f} G-evals/s")
+    print(json.dumps({
+        "metric": "fwd+adjoint G-evals/s (paper-scale IR step, adjoint with the centre gradient)",
+        "value": value, "unit": "G-evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 taps / f64 distances and sums",
+        "data": "synthetic (seeded vessel-tree phantom; b = A(x_true))",
+        "config": {"workload": "256x256x128 Gaussian kernels (0.1 mm), 1024 sensors on a 40 mm "
+                               "hemisphere, 4096 samples at 40 MHz, gradients for A, sigma and "
+                               "the centres, Adam on A and sigma",
+                   "kernels": M, "sensors": Nd, "samples": Nt, "parallelism": "single GPU"},
+        "fwd_kernel_ms": f_ms, "adj_kernel_ms": a_ms,
+        "kernel_source_sha256_16": kernel_source_hash()}), flush=True)
+
+
 def cpu_baseline_aniso(w, centres, sensors, A, S6, rows=16, stride=64):
     """The float64 anisotropic oracle on a bounded sample of the workload: the
     forward for `rows` sensors (all kernels), the adjoint with the covariance
@@ -690,6 +758,8 @@ def main():
                     help="benchmark the IR step with the ASSA operators (shared sigma)")
     ap.add_argument("--aniso", action="store_true",
                     help="the step with anisotropic kernels (covariances held fixed)")
+    ap.add_argument("--centres", action="store_true",
+                    help="the step whose adjoint also returns the centre gradient")
     ap.add_argument("--objective", action="store_true",
                     help="the step of Algorithm 2 in full: NPC latent, VCR regulariser, "
                          "warm-restart learning rate")
@@ -740,6 +810,9 @@ def main():
         return
     if args.aniso:
         bench_aniso(args)
+        return
+    if args.centres:
+        bench_centres(args)
         return
 
     import numpy as np
