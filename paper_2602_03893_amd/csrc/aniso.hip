@@ -43,7 +43,7 @@ struct alignas(64) AnisoRec {
   float A;                             // amplitude
   float fcz;                           // geometry: float32 centre (z)
   float sq;                            // sqrt(det Sigma)
-  float pk;                            // |A| sqrt(det) / lambda_min bound: |A| sqrt(det) tr^2 / (4 det)
+  float pk;                            // bound of |A| sqrt(det Sigma) / lambda_min
   float fcx, fcy;                      // geometry: float32 centre (x, y)
 };
 static_assert(sizeof(AnisoRec) == 64, "AnisoRec layout");
@@ -104,6 +104,33 @@ __global__ __launch_bounds__(256) void aniso_prep_kernel(
   const float a = A ? A[k] : 0.0f;
   const double sq = sqrt(det);
   const double tr = xx + yy + zz;
+  // 1/lambda_min for the fixed-point bound: the closed-form (trigonometric)
+  // smallest eigenvalue, lowered by 1e-6 and accepted only if Sigma - l I is
+  // then positive semidefinite; otherwise (or when it would be looser) the
+  // always valid tr^2 / (4 det) >= lambda_mid lambda_max / det = 1/lambda_min.
+  double inv_lmin = tr * tr / (4.0 * det);
+  {
+    const double p1 = xy * xy + xz * xz + yz * yz;
+    const double q = tr / 3.0;
+    const double p2 = (xx - q) * (xx - q) + (yy - q) * (yy - q) + (zz - q) * (zz - q) + 2.0 * p1;
+    double l3 = q;
+    if (p2 > 0.0) {
+      const double pp = sqrt(p2 / 6.0);
+      const double b11 = (xx - q) / pp, b22 = (yy - q) / pp, b33 = (zz - q) / pp;
+      const double b12 = xy / pp, b13 = xz / pp, b23 = yz / pp;
+      double rr = 0.5 * (b11 * (b22 * b33 - b23 * b23) - b12 * (b12 * b33 - b23 * b13) +
+                         b13 * (b12 * b23 - b22 * b13));
+      rr = fmin(1.0, fmax(-1.0, rr));
+      l3 = q + 2.0 * pp * cos(acos(rr) / 3.0 + 2.0943951023931957);
+    }
+    const double l = l3 * (1.0 - 1e-6);
+    const double cxx = xx - l, cyy = yy - l, czz = zz - l;
+    const double cdet =
+        cxx * (cyy * czz - yz * yz) - xy * (xy * czz - yz * xz) + xz * (xy * yz - cyy * xz);
+    if (l > 0.0 && cxx >= 0.0 && cyy >= 0.0 && czz >= 0.0 && cxx * cyy - xy * xy >= 0.0 &&
+        cxx * czz - xz * xz >= 0.0 && cyy * czz - yz * yz >= 0.0 && cdet >= 0.0)
+      inv_lmin = fmin(inv_lmin, 1.0 / l);
+  }
   AnisoRec &r = rec[i];
   r.sxx = s[0];
   r.syy = s[1];
@@ -113,7 +140,7 @@ __global__ __launch_bounds__(256) void aniso_prep_kernel(
   r.syz = s[5];
   r.A = a;
   r.sq = (float)sq;
-  r.pk = (float)(fabs((double)a) * sq * tr * tr / (4.0 * det));
+  r.pk = (float)(fabs((double)a) * sq * inv_lmin * (1.0 + 1e-6));
 }
 
 // sqrt(x) and 1/(2 sqrt(x)) for a positive normal float64 x: the float64

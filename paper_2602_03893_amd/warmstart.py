@@ -247,7 +247,7 @@ def main(argv=None):
     ap.add_argument("--workers", type=int, default=12)
     ap.add_argument("--train-budget", type=float, default=None, help="seconds")
     ap.add_argument("--params", default=None, help="skip training: load parameters (.npy)")
-    ap.add_argument("--out", default="gpurun_out/warmstart")
+    ap.add_argument("--out", default="warmstart_out")
     a = ap.parse_args(argv)
     os.makedirs(a.out, exist_ok=True)
     t_all = time.time()
