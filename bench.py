@@ -54,7 +54,7 @@ MEASURED_TRAFFIC = {
 
 # The same for the anisotropic kernels (aniso.hip).
 MEASURED_TRAFFIC_ANISO = {
-    "ed34c6d912b91f7c": {"aniso_forward_kernel": 2.263e9, "aniso_adjoint_kernel": 0.879e9},
+    "bf085ba8fa045c98": {"aniso_forward_kernel": 2.263e9, "aniso_adjoint_kernel": 0.879e9},
 }
 
 # The same for the ASSA kernels (assa.hip).

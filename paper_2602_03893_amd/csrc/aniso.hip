@@ -10,16 +10,18 @@
 //     p = A sqrt(det Sigma) / sigma_n^3 * d / (2r) * exp(-d^2 / (2 sigma_n^2)),
 //     sigma_n^2 = n^T Sigma n,  d = r - v t,  kept inside |d| <= n_sigma sigma_n
 // (Eq. (single_forward) exactly when Sigma = sigma^2 I).  The window depends
-// on the pair through sigma_n, so each pair is decided in float64 (distance,
-// sigma_n, first and last in-window sample, as the float64 definition) and
-// its taps run in float32 with the same Gaussian recurrence as the isotropic
-// operators, re-evaluated every kTapRunAniso taps.
+// on the pair through sigma_n: each pair goes through the isotropic
+// operators' float32 filter (filter.h) extended by sigma_n, and a pair whose
+// window end lies within the guard of a sample, or a block the planner keeps
+// in float64, is decided in float64 as the definition (distance, sigma_n,
+// first and last in-window sample).  Taps run in float32 with the same
+// Gaussian recurrence as the isotropic operators.
 //
 // Forward: one workgroup per (forward tile, 64 sensors), lane = sensor, the
-// waves take the tile's kernels in turn (wave-uniform loop); taps go into
-// the shared fixed-point LDS segment of the tile's time shell as in the
-// isotropic forward (the same segment bounds hold since every sigma_n is at
-// most sigma_max), then one float atomic per sample into y.
+// waves take the tile's reference blocks in turn (wave-uniform kernel loop);
+// taps go into the shared fixed-point LDS segment of the tile's time shell as
+// in the isotropic forward (the same segment bounds hold since every sigma_n
+// is at most sigma_max), then one float atomic per sample into y.
 // Adjoint: one workgroup per adjoint tile, lane = kernel; per stage of 64
 // sensors the residual over the tile's time shell is staged in LDS; per pair
 // the lane gathers its taps.  float32 within a stage, float64 across stages.
