@@ -22,6 +22,8 @@ _LAZY = {
     "gpair_forward": ("autograd", "gpair_forward"),
     "AssaForward": ("autograd", "AssaForward"),
     "assa_forward": ("autograd", "assa_forward"),
+    "AnisoForward": ("autograd", "AnisoForward"),
+    "aniso_forward": ("autograd", "aniso_forward"),
 }
 
 

@@ -56,3 +56,33 @@ class AssaForward(torch.autograd.Function):
 def assa_forward(x, sigma, plan):
     """Differentiable ASSA forward y = S(h * P_up(x)) for a bound Plan."""
     return AssaForward.apply(x, sigma, plan)
+
+
+class AnisoForward(torch.autograd.Function):
+    """y = A(x; Sigma) for anisotropic kernels (gpair_forward_aniso); the
+    backward is the hand-written adjoint (gpair_adjoint_aniso): dL/dA and
+    dL/dSigma for the six covariance parameters (xx, yy, zz, xy, xz, yz) at
+    fixed windows, taps recomputed.  sigma6 is (6, M)."""
+
+    @staticmethod
+    def forward(ctx, A, sigma6, plan):
+        A = A.contiguous()
+        sigma6 = sigma6.contiguous()
+        ctx.plan = plan
+        ctx.save_for_backward(A, sigma6)
+        return plan.forward_aniso(A, sigma6)
+
+    @staticmethod
+    def backward(ctx, grad_y):
+        A, sigma6 = ctx.saved_tensors
+        want_a = ctx.needs_input_grad[0]
+        want_s = ctx.needs_input_grad[1]
+        if not (want_a or want_s):
+            return None, None, None
+        gA, gS = ctx.plan.adjoint_aniso(A, sigma6, grad_y.contiguous(), want_sigma=want_s)
+        return (gA if want_a else None), (gS if want_s else None), None
+
+
+def aniso_forward(A, sigma6, plan):
+    """Differentiable y = A(x; Sigma) of anisotropic kernels for a bound Plan."""
+    return AnisoForward.apply(A, sigma6, plan)

@@ -45,7 +45,8 @@ struct alignas(64) AnisoRec {
   float A;                             // amplitude
   float fcz;                           // geometry: float32 centre (z)
   float sq;                            // sqrt(det Sigma)
-  float pk;                            // bound of |A| sqrt(det Sigma) / lambda_min
+  float pk;                            // bound of |A| sqrt(det Sigma) / lambda_min; sign
+                                       // bit set: every pair in float64 (ill-conditioned)
   float fcx, fcy;                      // geometry: float32 centre (x, y)
 };
 static_assert(sizeof(AnisoRec) == 64, "AnisoRec layout");
@@ -57,6 +58,11 @@ static_assert(offsetof(AnisoRec, fcz) == offsetof(KernelRec, fcz) &&
 
 constexpr int kAnisoWaves = 4;   // forward waves per workgroup
 constexpr int kTapRunAniso = 16; // taps between exact Gaussian factors
+// Largest condition number lambda_max/lambda_min of a covariance whose pairs
+// go through the float32 filter: sigma_n^2 from the float32 quadratic form is
+// then within about 24 kappa float32 units (6e-6 relative at 2.5), which keeps
+// the window ends inside the guard's margin and the taps near float32 accuracy.
+constexpr double kAnisoFilterKappa = 2.5;
 
 __device__ __forceinline__ int64_t xcd_logical_a(int64_t nlogical) {
   const int64_t per = (nlogical + kXcds - 1) / kXcds;
@@ -111,11 +117,13 @@ __global__ __launch_bounds__(256) void aniso_prep_kernel(
   // then positive semidefinite; otherwise (or when it would be looser) the
   // always valid tr^2 / (4 det) >= lambda_mid lambda_max / det = 1/lambda_min.
   double inv_lmin = tr * tr / (4.0 * det);
+  double l1 = tr;  // largest eigenvalue (tr bounds it)
   {
     const double p1 = xy * xy + xz * xz + yz * yz;
     const double q = tr / 3.0;
     const double p2 = (xx - q) * (xx - q) + (yy - q) * (yy - q) + (zz - q) * (zz - q) + 2.0 * p1;
     double l3 = q;
+    l1 = q;
     if (p2 > 0.0) {
       const double pp = sqrt(p2 / 6.0);
       const double b11 = (xx - q) / pp, b22 = (yy - q) / pp, b33 = (zz - q) / pp;
@@ -123,8 +131,11 @@ __global__ __launch_bounds__(256) void aniso_prep_kernel(
       double rr = 0.5 * (b11 * (b22 * b33 - b23 * b23) - b12 * (b12 * b33 - b23 * b13) +
                          b13 * (b12 * b23 - b22 * b13));
       rr = fmin(1.0, fmax(-1.0, rr));
-      l3 = q + 2.0 * pp * cos(acos(rr) / 3.0 + 2.0943951023931957);
+      const double phi = acos(rr) / 3.0;
+      l3 = q + 2.0 * pp * cos(phi + 2.0943951023931957);
+      l1 = q + 2.0 * pp * cos(phi);
     }
+    l1 *= 1.0 + 1e-6;
     const double l = l3 * (1.0 - 1e-6);
     const double cxx = xx - l, cyy = yy - l, czz = zz - l;
     const double cdet =
@@ -142,7 +153,12 @@ __global__ __launch_bounds__(256) void aniso_prep_kernel(
   r.syz = s[5];
   r.A = a;
   r.sq = (float)sq;
-  r.pk = (float)(fabs((double)a) * sq * inv_lmin * (1.0 + 1e-6));
+  // A kernel whose condition number exceeds kAnisoFilterKappa is decided in
+  // float64 for every pair (its sign bit of pk set): the float32 quadratic form
+  // u^T Sigma u loses about kappa float32 units of sigma_n^2 to cancellation,
+  // which would break the filter's error bound and the taps' accuracy.
+  const float pk = (float)(fabs((double)a) * sq * inv_lmin * (1.0 + 1e-6));
+  r.pk = l1 * inv_lmin > kAnisoFilterKappa ? -pk : pk;
 }
 
 // sqrt(x) and 1/(2 sqrt(x)) for a positive normal float64 x: the float64
@@ -231,8 +247,10 @@ __device__ __forceinline__ void aniso_exact(const double4 &s, const AnisoRec &k,
 // z -+ h_n about the pulse centre z (samples past Xi).  Returns true when an
 // end lies within kGuard of a sample (then the caller decides with
 // aniso_exact).  Its error is the isotropic filter's in z (below kGuard / 2 by
-// the planner's bound) plus about ten float32 units of h_n from sigma_n, so a
-// decision outside the guard equals the float64 one.
+// the planner's bound) plus the float32 error of h_n, at most about 12 kappa
+// float32 units of h_n <= h_max for kappa <= kAnisoFilterKappa (worse
+// conditioned kernels never come here), so a decision outside the guard
+// equals the float64 one.
 __device__ __forceinline__ bool aniso_filter(const BlockLane &bl, int kit, const AnisoRec &k,
                                              float nsig_inv_vdt, float inv_vdt_f, float smax2f,
                                              AnisoPair &p) {
@@ -330,7 +348,7 @@ __global__ __launch_bounds__(WAVES * kWave) void aniso_forward_kernel(
   // bounds any sample's tile sum; every wave adds the same values in the same
   // order, so all waves use the same unit.
   float psum = 0.0f;
-  for (int i = T.start + lane; i < T.start + T.count; i += kWave) psum += rec[i].pk;
+  for (int i = T.start + lane; i < T.start + T.count; i += kWave) psum += fabsf(rec[i].pk);
   for (int off = 32; off > 0; off >>= 1) psum += __shfl_xor(psum, off, kWave);
   const double r_low = fmax(R - T.rho, a.min_dist);
   const double bound = (double)psum * (1.0 + 1e-5) * 0.60653065971263342 / (2.0 * r_low);
@@ -357,7 +375,7 @@ __global__ __launch_bounds__(WAVES * kWave) void aniso_forward_kernel(
     for (int k = B.start; k < B.start + B.count; ++k) {
       const AnisoRec r = rec[k];
       AnisoPair p;
-      if (kit < 0 || aniso_filter(bl, kit, r, nsig_inv_vdt_f, inv_vdt_f, smax2f, p))
+      if (kit < 0 || signbit(r.pk) || aniso_filter(bl, kit, r, nsig_inv_vdt_f, inv_vdt_f, smax2f, p))
         aniso_exact(s, r, nb, a.inv_vdt, a.t0_over_dt, nsig_inv_vdt, a.smax2, p);
       const AnisoGauss gs = aniso_gauss(p.isn, vdt_f);
       // p = A sq / sigma_n^3 * (u Delta) / (2r) * exp2(c u^2), u in samples
@@ -486,7 +504,7 @@ __global__ __launch_bounds__(BLOCK) void aniso_adjoint_kernel(const double4 *__r
     float sA = 0.0f, sN[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     for (int js = 0; js < nsb; ++js) {
       AnisoPair p;
-      bool exact = kit < 0;
+      bool exact = kit < 0 || signbit(r.pk);
       if (!exact) {
         const float4 U = su[js];
         const float4 V = sv[js];

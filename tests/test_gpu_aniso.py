@@ -156,3 +156,53 @@ def test_admission_matches_the_eigenvalue_rule():
     n0 = plan.sigma_violations()
     plan.forward_aniso(dev(A), dev(S6))
     assert plan.sigma_violations() - n0 == expected
+
+
+def test_needle_and_pancake_covariances():
+    """Strongly anisotropic kernels (axes from 0.01 to 1 of sigma_max): from
+    some directions the window holds no sample or one, and the amplitude factor
+    sqrt(det)/sigma_n^3 varies by orders of magnitude across sensors."""
+    _say("case: toy workload, axes 0.01 .. 1 of sigma_max")
+    w = I.WORKLOADS["toy"]
+    cen, sen = I.geometry_arrays(w)
+    plan, g = plan_of(cen, sen, w.n_samples, w.smax)
+    A = I.uniform(w.n_kernels, seed=216, lo=-1.0, hi=1.0)
+    S6 = I.covariances(w.n_kernels, seed=217, lo=0.01 * w.smax, hi=w.smax)
+    delta = I.standard_normal((w.n_sensors, w.n_samples), seed=218)
+    check(plan, g, A, S6, delta, "needles and pancakes")
+
+
+def test_autograd_function_and_a_descent():
+    """The autograd Function: loss = 0.5 ||y(A, Sigma) - b||^2; its gradients
+    equal the oracle's adjoint of the residual for A and the six covariance
+    parameters, and Adam on A and Sigma lowers the loss."""
+    _say("case: toy workload, autograd through the anisotropic operators")
+    from paper_2602_03893_amd import aniso_forward
+    w = I.WORKLOADS["toy"]
+    cen, sen = I.geometry_arrays(w)
+    plan, g = plan_of(cen, sen, w.n_samples, w.smax)
+    S_true = I.covariances(w.n_kernels, seed=219, lo=0.4 * w.smax, hi=0.8 * w.smax)
+    b = O.forward_aniso(g, I.phantom(w).astype(np.float64), S_true.astype(np.float64).T)
+    A = torch.tensor(I.uniform(w.n_kernels, seed=220, lo=0.0, hi=0.5), device="cuda",
+                     requires_grad=True)
+    S6 = torch.tensor(I.covariances(w.n_kernels, seed=221, lo=0.4 * w.smax, hi=0.8 * w.smax),
+                      device="cuda", requires_grad=True)
+    bt = dev(b)
+    y = aniso_forward(A, S6, plan)
+    loss = 0.5 * torch.sum((y - bt) ** 2)
+    loss.backward()
+    resid = host(y - bt)
+    rA, rS = O.adjoint_aniso(g, host(A), host(S6).T, resid)
+    eA, eS = rel_l2(host(A.grad), rA), rel_l2(host(S6.grad).T, rS)
+    _say(f"  autograd gA {eA:.3e} gSigma {eS:.3e}")
+    assert eA <= TOL and eS <= TOL
+    opt = torch.optim.Adam([{"params": [A], "lr": 1e-2},
+                            {"params": [S6], "lr": 1e-3 * (0.6 * w.smax) ** 2}])
+    losses = []
+    for _ in range(8):
+        opt.zero_grad()
+        l = 0.5 * torch.sum((aniso_forward(A, S6, plan) - bt) ** 2)
+        l.backward()
+        opt.step()
+        losses.append(float(l))
+    assert losses[-1] < 0.9 * losses[0]
