@@ -39,6 +39,10 @@ Pins (what each function is checked against, in ``tests/``):
                      sigma/r -> 0; the dot-product test; central differences
                      in the six covariance parameters
                      (tests/test_oracle_aniso.py).
+ - ``ops.adjoint_aniso_centres``  the isotropic case against
+                     ``ops.adjoint_centres``; central differences of the pinned
+                     anisotropic forward in float32 centres; exact axis
+                     permutations.
  - ``physics``       Gauss-Legendre quadrature of the surface integral and a
                      numerical derivative of Eq. (pa_wave) (isotropic and
                      anisotropic p0).

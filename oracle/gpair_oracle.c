@@ -426,3 +426,65 @@ void oracle_adjoint_aniso(int64_t m, const float *cx, const float *cy, const flo
     }
   }
 }
+
+/* Gradient of <forward_aniso, delta> with respect to the kernel centres at
+ * fixed windows.  With u = s - c, r = |u|, n = u/r, sigma_n^2 = n^T Sigma n,
+ * d = r - v t and p = A sqrt(det)/sigma_n^3 d/(2r) exp(-d^2/(2 sigma_n^2)):
+ *   dp/dr (sigma_n held)  = A sqrt(det)/sigma_n^3 e/(2r) (1 - d^2/sigma_n^2 - d/r),
+ *   dp/d(sigma_n^2)       = p (d^2/(2 sigma_n^4) - 3/(2 sigma_n^2)),
+ *   dr/du = n,  d(sigma_n^2)/du = (2/r)(Sigma n - sigma_n^2 n),  du/dc = -I,
+ * so gc[k] = -sum_j sum_{n in W} delta (dp/dr n + dp/d(sigma_n^2) (2/r)(Sigma n -
+ * sigma_n^2 n)).  delta float64 [nd][nt]; gc float64 [m][3], overwritten. */
+void oracle_adjoint_aniso_centres(int64_t m, const float *cx, const float *cy, const float *cz,
+                                  const double *amp, const double *sigma6, int64_t nd,
+                                  const float *sensors, int64_t nt, double dt, double t0,
+                                  double v, double nsig, const double *delta, double *gc) {
+  int64_t k;
+#pragma omp parallel for schedule(static)
+  for (k = 0; k < m; ++k) {
+    const double *S = sigma6 + 6 * k;
+    double sq = sqrt(aniso_det(S));
+    double a = amp[k];
+    double g[3] = {0.0, 0.0, 0.0};
+    for (int64_t j = 0; j < nd; ++j) {
+      const float *s = sensors + 3 * j;
+      double ux = (double)s[0] - (double)cx[k];
+      double uy = (double)s[1] - (double)cy[k];
+      double uz = (double)s[2] - (double)cz[k];
+      double r2 = ux * ux + uy * uy + uz * uz;
+      double r = sqrt(r2);
+      double sn2 = aniso_sn2(S, ux, uy, uz, r2);
+      double sn = sqrt(sn2);
+      double half = nsig * sn;
+      int64_t lo, hi;
+      candidate_range(r, half, v, dt, t0, nt, &lo, &hi);
+      double T0 = 0.0, T1 = 0.0, T2 = 0.0, T3 = 0.0;
+      for (int64_t n = lo; n <= hi; ++n) {
+        double t = t0 + (double)n * dt;
+        double d = r - v * t;
+        if (fabs(d) <= half) {
+          double e = exp(-(d * d) / (2.0 * sn2));
+          double dl = delta[j * nt + n] * e;
+          T0 += dl;
+          T1 += dl * d;
+          T2 += dl * d * d;
+          T3 += dl * d * d * d;
+        }
+      }
+      double W0 = a * sq / (sn2 * sn) / (2.0 * r);
+      double dpr = W0 * (T0 - T2 / sn2 - T1 / r);
+      double dps = W0 * (T3 / (2.0 * sn2 * sn2) - 3.0 * T1 / (2.0 * sn2));
+      double nx = ux / r, ny = uy / r, nz = uz / r;
+      double Snx = S[0] * nx + S[3] * ny + S[4] * nz;
+      double Sny = S[3] * nx + S[1] * ny + S[5] * nz;
+      double Snz = S[4] * nx + S[5] * ny + S[2] * nz;
+      double f = dps * 2.0 / r;
+      g[0] -= dpr * nx + f * (Snx - sn2 * nx);
+      g[1] -= dpr * ny + f * (Sny - sn2 * ny);
+      g[2] -= dpr * nz + f * (Snz - sn2 * nz);
+    }
+    gc[3 * k + 0] = g[0];
+    gc[3 * k + 1] = g[1];
+    gc[3 * k + 2] = g[2];
+  }
+}

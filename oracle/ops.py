@@ -67,6 +67,10 @@ def _load():
     lib.oracle_adjoint_aniso.argtypes = [_i64, _f32p, _f32p, _f32p, _f64p, _f64p,
                                          _i64, _f32p, _i64, _dbl, _dbl, _dbl, _dbl,
                                          _f64p, _f64p, ctypes.c_void_p]
+    lib.oracle_adjoint_aniso_centres.restype = None
+    lib.oracle_adjoint_aniso_centres.argtypes = [_i64, _f32p, _f32p, _f32p, _f64p, _f64p,
+                                                 _i64, _f32p, _i64, _dbl, _dbl, _dbl, _dbl,
+                                                 _f64p, _f64p]
     lib.oracle_num_threads.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
     _lib = lib
@@ -214,3 +218,19 @@ def adjoint_aniso(g: Geometry, amp, sigma6, delta, want_sigma=True):
                              g.n_samples, g.dt, g.t0, g.c_sound, g.n_sigma, d, ga,
                              gs.ctypes.data_as(ctypes.c_void_p) if gs is not None else None)
     return ga, gs
+
+
+def adjoint_aniso_centres(g: Geometry, amp, sigma6, delta):
+    """gc float64 (M, 3): the gradient of <forward_aniso, delta> with respect to
+    the kernel centres, window membership held fixed."""
+    lib = _load()
+    a = _vec(amp, g.n_kernels, "amp")
+    s = _sigma6(sigma6, g.n_kernels)
+    d = np.ascontiguousarray(np.asarray(delta, dtype=np.float64))
+    if d.shape != (g.n_sensors, g.n_samples):
+        raise ValueError(f"delta: expected {(g.n_sensors, g.n_samples)}, got {d.shape}")
+    gc = np.empty((g.n_kernels, 3), dtype=np.float64)
+    lib.oracle_adjoint_aniso_centres(g.n_kernels, g.cx, g.cy, g.cz, a, s, g.n_sensors,
+                                     g.sensors, g.n_samples, g.dt, g.t0, g.c_sound,
+                                     g.n_sigma, d, gc)
+    return gc

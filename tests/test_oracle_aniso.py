@@ -180,3 +180,56 @@ def test_covariance_gradient_against_central_differences():
             assert abs(gS[k, a] - fd) <= 1e-5 * max(abs(fd), 1e-3 * np.abs(gS[k]).max()), (k, a)
             checked += 1
     assert checked >= 50
+
+
+def test_centre_gradient_isotropic_case_and_central_differences():
+    """The anisotropic centre gradient: with Sigma = sigma^2 I it equals the
+    isotropic oracle's centre gradient; with random covariances it matches
+    central differences of the forward in float32 centres (steps of ~4 nm; a
+    step that moves a window edge across a sample is skipped)."""
+    cen, sen, g, A = cloud(80, 12, seed=13)
+    rng = np.random.default_rng(14)
+    sig = rng.uniform(0.04e-3, 0.1e-3, 80)
+    s6 = np.zeros((80, 6))
+    s6[:, 0] = s6[:, 1] = s6[:, 2] = sig * sig
+    delta = rng.standard_normal((12, 512))
+    gc_iso = O.adjoint_centres(g, A, sig, delta)
+    gc_an = O.adjoint_aniso_centres(g, A, s6, delta)
+    assert np.max(np.abs(gc_an - gc_iso)) <= 1e-10 * np.abs(gc_iso).max()
+    s6 = random_cov(80, 0.03e-3, 0.1e-3, seed=15)
+    gc = O.adjoint_aniso_centres(g, A, s6, delta)
+    checked = 0
+    for k in range(0, 80, 4):
+        for ax in range(3):
+            cp, cm = cen[k].copy(), cen[k].copy()
+            cp[ax] = np.float32(cen[k, ax] + np.float32(4e-9))
+            cm[ax] = np.float32(cen[k, ax] - np.float32(4e-9))
+            gp = O.Geometry(cp[None], sen, g.n_samples, g.dt, g.t0, g.c_sound, g.n_sigma)
+            gm = O.Geometry(cm[None], sen, g.n_samples, g.dt, g.t0, g.c_sound, g.n_sigma)
+            yp = O.forward_aniso(gp, [A[k]], s6[k][None])
+            ym = O.forward_aniso(gm, [A[k]], s6[k][None])
+            if not np.array_equal(yp != 0, ym != 0):
+                continue
+            fd = (np.sum(yp * delta) - np.sum(ym * delta)) / (float(cp[ax]) - float(cm[ax]))
+            assert abs(gc[k, ax] - fd) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(gc).max()), (k, ax)
+            checked += 1
+    assert checked >= 45
+
+
+def test_centre_gradient_axis_permutation():
+    """(x, y, z) -> (y, z, -x) applied to the geometry and the covariances maps
+    the centre gradient by the same matrix."""
+    cen, sen, g, A = cloud(60, 10, seed=16)
+    s6 = random_cov(60, 0.03e-3, 0.1e-3, seed=17)
+    M = np.array([[0, 1, 0], [0, 0, 1], [-1, 0, 0]], dtype=np.float64)
+    cen2 = (cen.astype(np.float64) @ M.T).astype(np.float32)
+    sen2 = (np.asarray(sen, np.float64) @ M.T).astype(np.float32)
+    s62 = np.empty_like(s6)
+    for k in range(60):
+        c = M @ full(s6[k]) @ M.T
+        s62[k] = [c[0, 0], c[1, 1], c[2, 2], c[0, 1], c[0, 2], c[1, 2]]
+    g2 = O.Geometry(cen2, sen2, 512, I.DT, 0.0, I.C_SOUND, 3.0)
+    delta = np.random.default_rng(18).standard_normal((10, 512))
+    gc1 = O.adjoint_aniso_centres(g, A, s6, delta)
+    gc2 = O.adjoint_aniso_centres(g2, A, s62, delta)
+    assert np.max(np.abs(gc1 @ M.T - gc2)) <= 1e-10 * np.abs(gc1).max()
