@@ -326,6 +326,25 @@ gpair_status gpair_adjoint_aniso(gpair_plan p, const float *A, const float *sigm
                                  gpair_stream stream);
 
 /*
+ * gpair_adjoint_aniso plus the gradient with respect to the kernel centres at
+ * fixed windows: with u = s_j - c_k, n = u/r and the pressure p above,
+ *   gc_k = -sum_j sum_{n in W} delta_j[n] (dp/dr n + dp/d(sigma_n^2) (2/r)
+ *          (Sigma_k n - sigma_n^2 n)),
+ *   dp/dr (sigma_n held) = A sqrt(det)/sigma_n^3 e/(2r) (1 - d^2/sigma_n^2 - d/r),
+ *   dp/d(sigma_n^2) = p (d^2/(2 sigma_n^4) - 3/(2 sigma_n^2)),
+ * which is gpair_adjoint_centres' gradient when Sigma_k = sigma^2 I.  The
+ * plan's tiling stays that of plan creation (centres that move are taken up
+ * by a new plan).
+ *  A        device float32 [n_kernels] (required).
+ *  gcentres device float32 [n_kernels][3] (x, y, z), overwritten.
+ *  gA, gsigma6 as gpair_adjoint_aniso (gsigma6 may be NULL).
+ * Errors: INVALID_ARG, HIP.
+ */
+gpair_status gpair_adjoint_aniso_centres(gpair_plan p, const float *A, const float *sigma6,
+                                         const float *delta, float *gA, float *gsigma6,
+                                         float *gcentres, gpair_stream stream);
+
+/*
  * Synchronise `stream` and return in *count how many sigma_k values outside
  * (0, sigma_max] (and anisotropic covariances outside the admitted set) the
  * operators have met since the plan was created (each forward/adjoint call

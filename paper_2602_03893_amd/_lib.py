@@ -115,6 +115,8 @@ gpair_adjoint = _proto("gpair_adjoint", c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_
 gpair_forward_aniso = _proto("gpair_forward_aniso", c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp])
 gpair_adjoint_aniso = _proto("gpair_adjoint_aniso", c_i32,
                              [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp])
+gpair_adjoint_aniso_centres = _proto("gpair_adjoint_aniso_centres", c_i32,
+                                     [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp])
 gpair_adjoint_centres = _proto("gpair_adjoint_centres", c_i32,
                                [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp])
 gpair_sigma_violations = _proto("gpair_sigma_violations", c_i32,

@@ -220,6 +220,22 @@ class Plan:
               "gpair_adjoint_aniso")
         return gA, gS
 
+    def adjoint_aniso_centres(self, A, sigma6, delta, want_sigma=True):
+        """(gA [M], gsigma6 (6, M) or None, gcentres (M, 3)) float32 of
+        anisotropic kernels (gpair_adjoint_aniso_centres)."""
+        M = self.n_kernels
+        pa = _dev(A, "A", M, device=self.device)
+        ps = _dev(sigma6, "sigma6", 6 * M, device=self.device)
+        pd = _dev(delta, "delta", self.n_sensors * self.n_samples, device=self.device)
+        gA = torch.empty(M, dtype=torch.float32, device=self.device)
+        gS = torch.empty((6, M), dtype=torch.float32, device=self.device) if want_sigma else None
+        gC = torch.empty((M, 3), dtype=torch.float32, device=self.device)
+        check(_lib.gpair_adjoint_aniso_centres(self._h, pa, ps, pd, _dev(gA, "gA", M),
+                                               _dev(gS, "gsigma6", 6 * M) if want_sigma else None,
+                                               _dev(gC, "gcentres", 3 * M), _stream()),
+              "gpair_adjoint_aniso_centres")
+        return gA, gS, gC
+
     def residual(self, y, b, scale=1.0, delta=None):
         """norms (2,) float64 on device = (sum (y-b)^2, sum b^2); writes
         delta = scale (y - b) when `delta` is given (may be y itself)."""

@@ -448,12 +448,17 @@ struct AnisoAdjArgs {
   const float *delta;
   float *gA;
   float *gS;  // [6][M] caller order, or null
+  float *gC;  // [M][3] caller order (centre gradient), or null
   int64_t nlogical, M;
   int32_t Nd, Nt, L;
   double inv_vdt, t0_over_dt, hmax, vdt, nsig, smax2;
 };
 
-template <int BLOCK, bool SIGMA>
+// SIGMA: also the covariance gradient; CENTRES: also the centre gradient,
+// -sum delta (dp/dr n + dp/d(sigma_n^2) (2/r)(Sigma n - sigma_n^2 n)), whose
+// direction terms are formed in float64 (Sigma n - sigma_n^2 n cancels by
+// about the condition number of Sigma).
+template <int BLOCK, bool SIGMA, bool CENTRES = false>
 __global__ __launch_bounds__(BLOCK) void aniso_adjoint_kernel(const double4 *__restrict__ sens,
                                                               AnisoAdjArgs a) {
   extern __shared__ float stage[];  // [kAdjSensorsPerStage][L]
@@ -476,6 +481,7 @@ __global__ __launch_bounds__(BLOCK) void aniso_adjoint_kernel(const double4 *__r
   const float nsig_inv_vdt_f = (float)nsig_inv_vdt, smax2f = (float)a.smax2;
 
   double accA = 0.0, accN[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double accC[3] = {0.0, 0.0, 0.0};
   for (int j0 = 0; j0 < a.Nd; j0 += kAdjSensorsPerStage) {
     const int nsb = min(kAdjSensorsPerStage, a.Nd - j0);
     __syncthreads();  // the previous stage has been consumed
@@ -522,16 +528,23 @@ __global__ __launch_bounds__(BLOCK) void aniso_adjoint_kernel(const double4 *__r
         aniso_exact(sens[j0 + js], r, nbs[js], a.inv_vdt, a.t0_over_dt, nsig_inv_vdt, a.smax2, p);
       const AnisoGauss gs = aniso_gauss(p.isn, vdt_f);
       const float *rp = stage + js * a.L + p.o;
-      float s1 = 0.0f, s3 = 0.0f;
+      // In samples: s0 = sum delta e, s1 = sum delta u e, s2 = sum delta u^2 e,
+      // s3 = sum delta u^3 e.
+      float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
       for (int i0 = 0; i0 < p.ntap; i0 += kTapRunAniso) {
         float d = p.d0 - (float)i0;
         float f = __builtin_amdgcn_exp2f(gs.c * d * d);
         float q = __builtin_amdgcn_exp2f(fmaf(gs.k1, d, gs.c));
         const int iend = min(i0 + kTapRunAniso, p.ntap);
         for (int ii = i0; ii < iend; ++ii) {
-          const float pd = rp[ii] * f * d;
+          const float t = rp[ii] * f;
+          const float pd = t * d;
           s1 += pd;
-          if (SIGMA) s3 = fmaf(pd, d * d, s3);
+          if (SIGMA || CENTRES) s3 = fmaf(pd, d * d, s3);
+          if (CENTRES) {
+            s0 += t;
+            s2 = fmaf(pd, d, s2);
+          }
           d -= 1.0f;
           f *= q;
           q *= gs.rq;
@@ -540,10 +553,32 @@ __global__ __launch_bounds__(BLOCK) void aniso_adjoint_kernel(const double4 *__r
       // W = sqrt(det) / sigma_n^3 * Delta / (2r): gA += W s1
       const float W = r.sq * (p.isn * p.isn * p.isn) * hvdt * p.rinv;
       sA = fmaf(W, s1, sA);
+      const float iu = vdt_f * p.isn;
+      // W / (2 sigma_n^2) (s3 (Delta/sigma_n)^2 - 3 s1): the sigma_n^2 factor
+      const float G = W * 0.5f * (p.isn * p.isn) * fmaf(s3, iu * iu, -3.0f * s1);
+      if (CENTRES) {
+        // dp/dr part: A sqrt(det)/sigma_n^3/(2r) (s0 - (Delta/sigma_n)^2 s2 - (Delta/r) s1)
+        const float dpr = r.A * W * inv_vdt_f *
+                          (s0 - iu * iu * s2 - vdt_f * p.rinv * s1);
+        const double dps = (double)r.A * (double)G;
+        const double4 sj = sens[j0 + js];
+        const double ux = sj.x - (double)r.fcx, uy = sj.y - (double)r.fcy,
+                     uz = sj.z - (double)r.fcz;
+        double hr;
+        sqrt_and_half_rinv(fma(uz, uz, fma(uy, uy, ux * ux)), hr);
+        const double ri = 2.0 * hr;
+        const double nx = ux * ri, ny = uy * ri, nz = uz * ri;
+        const double Snx = fma((double)r.sxx, nx, fma((double)r.sxy, ny, (double)r.sxz * nz));
+        const double Sny = fma((double)r.sxy, nx, fma((double)r.syy, ny, (double)r.syz * nz));
+        const double Snz = fma((double)r.sxz, nx, fma((double)r.syz, ny, (double)r.szz * nz));
+        const double sn2 = fma(nx, Snx, fma(ny, Sny, nz * Snz));
+        const double f2 = dps * 2.0 * ri;
+        accC[0] -= fma((double)dpr, nx, f2 * fma(-sn2, nx, Snx));
+        accC[1] -= fma((double)dpr, ny, f2 * fma(-sn2, ny, Sny));
+        accC[2] -= fma((double)dpr, nz, f2 * fma(-sn2, nz, Snz));
+      }
       if (SIGMA) {
-        // W / (2 sigma_n^2) (s3 (Delta/sigma_n)^2 - 3 s1) along n n^T
-        const float iu = vdt_f * p.isn;
-        const float G = W * 0.5f * (p.isn * p.isn) * fmaf(s3, iu * iu, -3.0f * s1);
+        // G along n n^T
         sN[0] = fmaf(G * p.nx, p.nx, sN[0]);
         sN[1] = fmaf(G * p.ny, p.ny, sN[1]);
         sN[2] = fmaf(G * p.nz, p.nz, sN[2]);
@@ -561,6 +596,10 @@ __global__ __launch_bounds__(BLOCK) void aniso_adjoint_kernel(const double4 *__r
   if (!live) return;
   const int32_t k = a.perm[i];
   a.gA[k] = (float)accA;
+  if (CENTRES) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.gC[3 * (int64_t)k + c] = (float)accC[c];
+  }
   if (SIGMA) {
     const double xx = r.sxx, yy = r.syy, zz = r.szz, xy = r.sxy, xz = r.sxz, yz = r.syz;
     const double det = xx * (yy * zz - yz * yz) - xy * (xy * zz - yz * xz) + xz * (xy * yz - yy * xz);
@@ -615,7 +654,7 @@ hipError_t launch_aniso_forward(const gpair_plan_s *p, float *y, hipStream_t s) 
 }
 
 hipError_t launch_aniso_adjoint(const gpair_plan_s *p, const float *delta, float *gA,
-                                float *gsig6, hipStream_t s) {
+                                float *gsig6, float *gcentres, hipStream_t s) {
   AnisoAdjArgs a;
   a.rec = (const AnisoRec *)ws_krec(p);
   a.tiles = ws_atiles(p);
@@ -623,6 +662,7 @@ hipError_t launch_aniso_adjoint(const gpair_plan_s *p, const float *delta, float
   a.delta = delta;
   a.gA = gA;
   a.gS = gsig6;
+  a.gC = gcentres;
   a.nlogical = (int64_t)p->host.atiles.size();
   a.M = p->M;
   a.Nd = p->Nd;
@@ -639,7 +679,11 @@ hipError_t launch_aniso_adjoint(const gpair_plan_s *p, const float *delta, float
   const unsigned int grid = xcd_grid_a(a.nlogical);
   const double4 *sens = (const double4 *)ws_sens(p);
 #define GPAIR_ANISO_ADJ(B)                                                                 \
-  if (gsig6)                                                                               \
+  if (gcentres && gsig6)                                                                   \
+    aniso_adjoint_kernel<B, true, true><<<grid, B, lds, s>>>(sens, a);                     \
+  else if (gcentres)                                                                       \
+    aniso_adjoint_kernel<B, false, true><<<grid, B, lds, s>>>(sens, a);                    \
+  else if (gsig6)                                                                          \
     aniso_adjoint_kernel<B, true><<<grid, B, lds, s>>>(sens, a);                           \
   else                                                                                     \
     aniso_adjoint_kernel<B, false><<<grid, B, lds, s>>>(sens, a);

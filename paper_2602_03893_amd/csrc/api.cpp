@@ -277,7 +277,21 @@ gpair_status gpair_adjoint_aniso(gpair_plan p, const float *A, const float *sigm
   hipError_t e = launch_aniso_prep(p, A, sigma6, s);
   if (e != hipSuccess) return GPAIR_ERR_HIP;
   timer_begin(p, GPAIR_TIMER_ADJOINT, s);
-  e = launch_aniso_adjoint(p, delta, gA, gsigma6, s);
+  e = launch_aniso_adjoint(p, delta, gA, gsigma6, nullptr, s);
+  timer_end(p, GPAIR_TIMER_ADJOINT, s);
+  return hip_status(e);
+}
+
+gpair_status gpair_adjoint_aniso_centres(gpair_plan p, const float *A, const float *sigma6,
+                                         const float *delta, float *gA, float *gsigma6,
+                                         float *gcentres, gpair_stream stream) {
+  if (!bound(p) || !A || !sigma6 || !delta || !gA || !gcentres) return GPAIR_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  p->prepared = 0;
+  hipError_t e = launch_aniso_prep(p, A, sigma6, s);
+  if (e != hipSuccess) return GPAIR_ERR_HIP;
+  timer_begin(p, GPAIR_TIMER_ADJOINT, s);
+  e = launch_aniso_adjoint(p, delta, gA, gsigma6, gcentres, s);
   timer_end(p, GPAIR_TIMER_ADJOINT, s);
   return hip_status(e);
 }

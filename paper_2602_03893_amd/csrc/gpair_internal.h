@@ -205,12 +205,12 @@ hipError_t launch_forward(const gpair_plan_s *p, float *y, hipStream_t s);
 hipError_t launch_adjoint(const gpair_plan_s *p, const float *delta, float *gA,
                           float *gsigma, float *gcentres, hipStream_t s);
 // Anisotropic kernels (aniso.hip): records from (A, Sigma), forward into y
-// (zeroed by the caller), adjoint (gsig6 may be null).
+// (zeroed by the caller), adjoint (gsig6 and gcentres may be null).
 hipError_t launch_aniso_prep(const gpair_plan_s *p, const float *A, const float *sig6,
                              hipStream_t s);
 hipError_t launch_aniso_forward(const gpair_plan_s *p, float *y, hipStream_t s);
 hipError_t launch_aniso_adjoint(const gpair_plan_s *p, const float *delta, float *gA,
-                                float *gsig6, hipStream_t s);
+                                float *gsig6, float *gcentres, hipStream_t s);
 hipError_t launch_residual(const gpair_plan_s *p, const float *y, const float *b,
                            float scale, float *delta, double *norms,
                            hipStream_t s);
