@@ -54,7 +54,7 @@ MEASURED_TRAFFIC = {
 
 # The same for the anisotropic kernels (aniso.hip).
 MEASURED_TRAFFIC_ANISO = {
-    "bf085ba8fa045c98": {"aniso_forward_kernel": 2.263e9, "aniso_adjoint_kernel": 0.879e9},
+    "a306d241e0be26d2": {"aniso_forward_kernel": 2.263e+09, "aniso_adjoint_kernel": 8.79e+08},
 }
 
 # The same for the ASSA kernels (assa.hip).
