@@ -32,6 +32,8 @@ CUS, CLOCK_HZ = 256, 2.4e9  # MI355X compute units and peak engine clock
 FLOP_TAP_FWD = 7      # d, d^2, scale, exp, * d, * A/(2r), accumulate
 FLOP_TAP_ADJ = 10     # d, d^2, scale, exp, * d, * delta, acc A, * d^2, acc sigma, (d^3 reuse)
 FLOP_PAIR = 25        # distance (3 sub, 3 fma, sqrt), window bounds, 1/(2r), tap setup
+FLOP_TAP_CENTRES = 5  # the centre gradient's extra sums per tap (delta e, delta u^2 e)
+FLOP_PAIR_CENTRES = 16  # its per-pair combination along (c - s)/r
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (dense amplitudes,
 # scaled by the counts a 256 MiB device copy gives: fetch x2.0, write x1.0), keyed
@@ -54,7 +56,7 @@ MEASURED_TRAFFIC = {
 
 # The same for the anisotropic kernels (aniso.hip).
 MEASURED_TRAFFIC_ANISO = {
-    "a306d241e0be26d2": {"aniso_forward_kernel": 2.263e+09, "aniso_adjoint_kernel": 8.79e+08},
+    "b0b6ea796235c811": {"aniso_forward_kernel": 2.263e+09, "aniso_adjoint_kernel": 8.786e+08},
 }
 
 # The same for the ASSA kernels (assa.hip).
@@ -111,7 +113,7 @@ def measure_peaks():
     return out
 
 
-def cpu_baseline(w, centres, sensors, A, sigma_val, rows=32, stride=32):
+def cpu_baseline(w, centres, sensors, A, sigma_val, rows=192, stride=6):
     """The float64 oracle on a bounded sample of the same workload: the forward
     for `rows` sensors (all kernels) and the adjoint for every `stride`-th
     kernel (all sensors).  Returns the rate in G pair-evaluations/s."""
@@ -589,7 +591,13 @@ def bench_centres(args):
     value = 2.0 * float(M) * Nd * args.steps / elapsed / 1e9
     log(f"bench --centres: {ms_step:.2f} ms/step, forward kernel {f_ms:.2f} ms, adjoint kernel "
         f"(A, sigma, centres) {a_ms:.2f} ms, {value:.1f} G-evals/s")
-    print(json.dumps({
+    # in-window taps per operator at the step's sigma; the centre mode adds
+    # three sums per tap and the direction terms per pair
+    taps = float(torch.sum(sigma.double())) * 2 * w.n_sigma / (w.c_sound * w.dt) * Nd
+    pairs = float(M) * Nd
+    flop = (FLOP_TAP_ADJ + FLOP_TAP_CENTRES) * taps + (FLOP_PAIR + FLOP_PAIR_CENTRES) * pairs
+    achieved = flop / (a_ms * 1e-3) / 1e12
+    out = {
         "metric": "fwd+adjoint G-evals/s (paper-scale IR step, adjoint with the centre gradient)",
         "value": value, "unit": "G-evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
@@ -600,10 +608,36 @@ def bench_centres(args):
                                "the centres, Adam on A and sigma",
                    "kernels": M, "sensors": Nd, "samples": Nt, "parallelism": "single GPU"},
         "fwd_kernel_ms": f_ms, "adj_kernel_ms": a_ms,
-        "kernel_source_sha256_16": kernel_source_hash()}), flush=True)
+        "roofline": {"bound": "alu", "kernel": "adjoint_centres_kernel", "achieved": achieved,
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel_source_sha256_16": kernel_source_hash()}}
+    if not args.no_cpu_baseline:
+        log("bench --centres: timing the float64 oracle's centre gradient on a sample")
+        out["cpu_baseline"] = cpu_baseline_centres(w, centres, sensors, I.phantom(w), sig0)
+    print(json.dumps(out), flush=True)
 
 
-def cpu_baseline_aniso(w, centres, sensors, A, S6, rows=16, stride=64):
+def cpu_baseline_centres(w, centres, sensors, A, sigma_val, stride=4):
+    """The float64 oracle's centre gradient for every `stride`-th kernel (all
+    sensors): a bounded sample of the centre-gradient adjoint."""
+    import numpy as np
+    from oracle import ops as O
+    from paper_2602_03893_amd import inputs as I
+    g = O.Geometry(centres, sensors, w.n_samples, w.dt, w.t0, w.c_sound, w.n_sigma)
+    ks = np.arange(0, w.n_kernels, stride)
+    delta = I.standard_normal((w.n_sensors, w.n_samples), seed=99, dtype=np.float64)
+    t = time.perf_counter()
+    O.adjoint_centres(g.subset_kernels(ks), A[ks].astype(np.float64),
+                      np.full(len(ks), sigma_val), delta)
+    el = time.perf_counter() - t
+    return {"value": len(ks) * w.n_sensors / el / 1e9, "unit": "G-evals/s",
+            "cores": O.num_threads(), "kind": "oracle", "cpu_model": host_cpu_model(),
+            "sample": (f"float64 oracle centre gradient on {len(ks)} kernels x {w.n_sensors} "
+                       f"sensors ({el:.2f} s); rate = pairs / time")}
+
+
+def cpu_baseline_aniso(w, centres, sensors, A, S6, rows=160, stride=8):
     """The float64 anisotropic oracle on a bounded sample of the workload: the
     forward for `rows` sensors (all kernels), the adjoint with the covariance
     gradient for every `stride`-th kernel (all sensors)."""

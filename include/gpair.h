@@ -304,8 +304,10 @@ gpair_status gpair_adjoint_prepared(gpair_plan p, const float *delta, float *gA,
  *          positive definite or whose largest eigenvalue exceeds sigma_max^2
  *          is replaced by sigma_max^2 I for that kernel and counted (see
  *          gpair_sigma_violations); the call still returns GPAIR_OK.
- *  y       device float32 [n_sensors][n_samples], overwritten (forward; float
- *          atomics: the plan's `deterministic` option does not apply here).
+ *  y       device float32 [n_sensors][n_samples], overwritten (forward; with
+ *          the plan's `deterministic` option the tile sums go through the same
+ *          64-bit integer flush as gpair_forward's, so y is bitwise
+ *          reproducible).
  *  delta   device float32 [n_sensors][n_samples] (adjoint).
  *  gA      device float32 [n_kernels], overwritten: the transpose of the
  *          forward applied to delta.

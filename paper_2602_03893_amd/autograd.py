@@ -10,13 +10,35 @@ of Eq. (single_forward) with respect to sigma.
 import torch
 
 
+def _checked(plan, call, what):
+    """Run `call` and raise if it met widths the operators had to clamp (or
+    covariances they had to replace): the result and its backward would then
+    belong to another function than the one the caller's parameters define.
+    Reads the plan's violation counter before and after (two stream syncs)."""
+    before = plan.sigma_violations()
+    out = call()
+    met = plan.sigma_violations() - before
+    if met:
+        raise ValueError(f"{what}: {met} kernel(s) outside the admitted range (sigma in "
+                         f"(0, sigma_max], covariances positive definite with largest "
+                         f"eigenvalue <= sigma_max^2); project the parameters first, or "
+                         f"pass check=False to accept the clamped operator")
+    return out
+
+
 class GpairForward(torch.autograd.Function):
+    """y = A(x; sigma) (gpair_forward); `check` (default True) raises
+    ValueError when a sigma_k lies outside (0, sigma_max], which the operator
+    would otherwise clamp, giving the gradient of the clamped function."""
+
     @staticmethod
-    def forward(ctx, A, sigma, plan):
+    def forward(ctx, A, sigma, plan, check=True):
         A = A.contiguous()
         sigma = sigma.contiguous()
         ctx.plan = plan
         ctx.save_for_backward(A, sigma)
+        if check:
+            return _checked(plan, lambda: plan.forward(A, sigma), "gpair_forward")
         return plan.forward(A, sigma)
 
     @staticmethod
@@ -25,14 +47,15 @@ class GpairForward(torch.autograd.Function):
         want_a = ctx.needs_input_grad[0]
         want_s = ctx.needs_input_grad[1]
         if not (want_a or want_s):
-            return None, None, None
+            return None, None, None, None
         gA, gS = ctx.plan.adjoint(A, sigma, grad_y.contiguous(), want_sigma=want_s)
-        return (gA if want_a else None), (gS if want_s else None), None
+        return (gA if want_a else None), (gS if want_s else None), None, None
 
 
-def gpair_forward(A, sigma, plan):
-    """Differentiable y = A(x; sigma) for the given bound Plan."""
-    return GpairForward.apply(A, sigma, plan)
+def gpair_forward(A, sigma, plan, check=True):
+    """Differentiable y = A(x; sigma) for the given bound Plan (see
+    GpairForward for `check`)."""
+    return GpairForward.apply(A, sigma, plan, check)
 
 
 class AssaForward(torch.autograd.Function):
@@ -62,14 +85,18 @@ class AnisoForward(torch.autograd.Function):
     """y = A(x; Sigma) for anisotropic kernels (gpair_forward_aniso); the
     backward is the hand-written adjoint (gpair_adjoint_aniso): dL/dA and
     dL/dSigma for the six covariance parameters (xx, yy, zz, xy, xz, yz) at
-    fixed windows, taps recomputed.  sigma6 is (6, M)."""
+    fixed windows, taps recomputed.  sigma6 is (6, M).  `check` (default
+    True) raises ValueError when a covariance lies outside the admitted set,
+    which the operator would otherwise replace by sigma_max^2 I."""
 
     @staticmethod
-    def forward(ctx, A, sigma6, plan):
+    def forward(ctx, A, sigma6, plan, check=True):
         A = A.contiguous()
         sigma6 = sigma6.contiguous()
         ctx.plan = plan
         ctx.save_for_backward(A, sigma6)
+        if check:
+            return _checked(plan, lambda: plan.forward_aniso(A, sigma6), "gpair_forward_aniso")
         return plan.forward_aniso(A, sigma6)
 
     @staticmethod
@@ -78,11 +105,12 @@ class AnisoForward(torch.autograd.Function):
         want_a = ctx.needs_input_grad[0]
         want_s = ctx.needs_input_grad[1]
         if not (want_a or want_s):
-            return None, None, None
+            return None, None, None, None
         gA, gS = ctx.plan.adjoint_aniso(A, sigma6, grad_y.contiguous(), want_sigma=want_s)
-        return (gA if want_a else None), (gS if want_s else None), None
+        return (gA if want_a else None), (gS if want_s else None), None, None
 
 
-def aniso_forward(A, sigma6, plan):
-    """Differentiable y = A(x; Sigma) of anisotropic kernels for a bound Plan."""
-    return AnisoForward.apply(A, sigma6, plan)
+def aniso_forward(A, sigma6, plan, check=True):
+    """Differentiable y = A(x; Sigma) of anisotropic kernels for a bound Plan
+    (see AnisoForward for `check`)."""
+    return AnisoForward.apply(A, sigma6, plan, check)

@@ -29,6 +29,7 @@
 //   dp/dSigma = p [Sigma^-1 / 2 + (d^2 / (2 sigma_n^4) - 3 / (2 sigma_n^2)) n n^T],
 // an off-diagonal parameter standing for both symmetric entries (twice the
 // matrix entry).
+#include <algorithm>
 #include <cmath>
 
 #include "filter.h"
@@ -296,7 +297,43 @@ struct AnisoFwdArgs {
   int32_t ntiles, nblocks;
   int32_t Nd, Nt, nsg, L;
   double inv_vdt, t0_over_dt, hmax, vdt, nsig, smax2, min_dist;
+  long long *y64;          // deterministic flush: int64 [Nd][Nt] in units of *det_unit
+  const double *det_unit;  // the global unit (device), set before the launch
 };
+
+// Deterministic forward: the global unit G = 2^-62 e^{-1/2}/(2 min_dist)
+// sum_k |pk_k| (a bound on every sample of y), from per-block partial sums
+// reduced in a fixed order; then y = G y64.
+__global__ __launch_bounds__(256) void aniso_det_partial_kernel(const AnisoRec *__restrict__ rec,
+                                                               int64_t M, double *partials) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < M; i += (int64_t)gridDim.x * 256)
+    acc += fabs((double)rec[i].pk);
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = sh[0];
+}
+
+__global__ void aniso_det_unit_kernel(const double *partials, int nblocks, double scale,
+                                      double *unit) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double sum = 0.0;
+  for (int b = 0; b < nblocks; ++b) sum += partials[b];
+  *unit = sum * scale;
+}
+
+__global__ __launch_bounds__(256) void aniso_det_finish_kernel(const long long *__restrict__ y64,
+                                                              const double *unit, float *y,
+                                                              int64_t n) {
+  const double G = *unit;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    y[i] = (float)((double)y64[i] * G);
+}
 
 __device__ __forceinline__ void lds_add_fx(int *p, float v) {
   int n;
@@ -321,7 +358,7 @@ __device__ __forceinline__ void aniso_taps(int *pa, float f, float q, float d, f
   }
 }
 
-template <int WAVES>
+template <int WAVES, bool DET>
 __global__ __launch_bounds__(WAVES * kWave) void aniso_forward_kernel(
     const AnisoRec *__restrict__ rec, AnisoFwdArgs a) {
   extern __shared__ int seg[];  // [L][64]
@@ -418,13 +455,37 @@ __global__ __launch_bounds__(WAVES * kWave) void aniso_forward_kernel(
   }
   __syncthreads();
 
-  // Back to float32 (each lane's own unit), row c rotated by c columns, then
-  // one coalesced float atomic per sample (as the isotropic forward).
+  // Back to float32 (each lane's own unit; DET: kept as integers), row c
+  // rotated by c columns, then one coalesced atomic per sample (as the
+  // isotropic forward).
   for (int cr = wave; cr < a.L; cr += WAVES) {
     const int v = col[cr * kWave];
-    seg[cr * kWave + ((lane + cr) & (kWave - 1))] = __float_as_int((float)v * unit);
+    seg[cr * kWave + ((lane + cr) & (kWave - 1))] = DET ? v : __float_as_int((float)v * unit);
   }
   __syncthreads();
+  if (DET) {
+    // Each sample's tile sum (an integer in units of bound 2^-30) goes to the
+    // global unit G, rounded to the nearest integer, and is added with a
+    // 64-bit integer atomic: the rounding depends only on the tile's own sum
+    // and integer addition is exact, so y is the same bit for bit whatever the
+    // order of the tiles.  G is 2^-62 of a bound on every sample of y.
+    const double fac = bound * 0x1p-30 / *a.det_unit;
+    for (int row = wave; row < kWave; row += WAVES) {
+      const int jr = sg * kWave + row;
+      if (jr >= a.Nd) break;
+      const int nbr = __builtin_amdgcn_readlane(nb, row);
+      const double fr = __shfl(fac, row, kWave);
+      long long *yrow = a.y64 + (int64_t)jr * a.Nt;
+      for (int cs = lane; cs < a.L; cs += kWave) {
+        const int n = nbr + cs;
+        const int v = seg[cs * kWave + ((row + cs) & (kWave - 1))];
+        if (n >= 0 && n < a.Nt && v != 0)
+          __hip_atomic_fetch_add(yrow + n, (long long)llrint((double)v * fr), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    return;
+  }
   for (int row = wave; row < kWave; row += WAVES) {
     const int jr = sg * kWave + row;
     if (jr >= a.Nd) break;
@@ -647,9 +708,29 @@ hipError_t launch_aniso_forward(const gpair_plan_s *p, float *y, hipStream_t s) 
   const double smax = p->sigma_max * (1.0 + 1e-6);
   a.smax2 = smax * smax;
   a.min_dist = p->min_dist;
+  a.y64 = nullptr;
+  a.det_unit = nullptr;
   const size_t lds = (size_t)p->Lf * kWave * sizeof(int);
-  aniso_forward_kernel<kAnisoWaves><<<xcd_grid_a(a.nlogical), kAnisoWaves * kWave, lds, s>>>(
-      (const AnisoRec *)ws_krec(p), a);
+  const unsigned int grid = xcd_grid_a(a.nlogical);
+  const AnisoRec *rec = (const AnisoRec *)ws_krec(p);
+  if (!p->deterministic) {
+    aniso_forward_kernel<kAnisoWaves, false><<<grid, kAnisoWaves * kWave, lds, s>>>(rec, a);
+    return hipGetLastError();
+  }
+  const int64_t n = (int64_t)p->Nd * p->Nt;
+  a.y64 = ws_det(p);
+  double *unit = (double *)(a.y64 + n);
+  double *partials = ws_partials(p);
+  aniso_det_partial_kernel<<<kResidualBlocks, 256, 0, s>>>(rec, p->M, partials);
+  aniso_det_unit_kernel<<<1, 64, 0, s>>>(
+      partials, kResidualBlocks, (1.0 + 1e-5) * 0.60653065971263342 / (2.0 * p->min_dist) * 0x1p-62,
+      unit);
+  a.det_unit = unit;
+  hipError_t e = launch_fill((float *)a.y64, 2 * n, 0.0f, s);  // int64 zero = two float zeros
+  if (e != hipSuccess) return e;
+  aniso_forward_kernel<kAnisoWaves, true><<<grid, kAnisoWaves * kWave, lds, s>>>(rec, a);
+  aniso_det_finish_kernel<<<(unsigned int)std::min<int64_t>((n + 255) / 256, 16384), 256, 0, s>>>(
+      a.y64, a.det_unit, y, n);
   return hipGetLastError();
 }
 

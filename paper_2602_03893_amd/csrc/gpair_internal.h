@@ -126,7 +126,11 @@ static_assert(offsetof(AssaRec, fcz) == offsetof(KernelRec, fcz) &&
 
 constexpr int kWave = 64;
 constexpr int kAdjSensorsPerStage = 64; // sensors staged per LDS refill
-constexpr int kMaxSegmentBytes = 63 * 1024; // dynamic LDS per workgroup (64 KiB less static use)
+// Cap of the dynamic LDS segment per workgroup.  The kernels' static LDS comes
+// on top (at most 4.25 KiB: the direct adjoint's staged sensors, tap counts
+// and ranking), so a workgroup asks for at most 67.25 KiB of gfx950's 160 KiB;
+// the planner shrinks tiles until their segments fit the cap.
+constexpr int kMaxSegmentBytes = 63 * 1024;
 constexpr int kResidualBlocks = 1024;
 constexpr int kXcds = 8;                // MI355X: 8 accelerator dies
 

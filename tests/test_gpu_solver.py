@@ -160,3 +160,27 @@ def test_autograd_matches_oracle_and_differences(toy):
         lm = 0.5 * np.sum((O.forward(g, A0, sm) - b) ** 2)
         fd = (lp - lm) / (2 * h)
         assert abs(gs[k] - fd) <= 1e-3 * max(abs(fd), 1e-3 * np.abs(gs).max()), (k, gs[k], fd)
+
+
+def test_autograd_rejects_widths_the_operator_would_clamp(toy):
+    """A sigma_k outside (0, sigma_max] makes the autograd forward raise
+    (the operator would clamp it and differentiate another function);
+    check=False accepts the clamped operator, whose output equals the one at
+    the clamped widths."""
+    from paper_2602_03893_amd import gpair_forward
+    w, plan, g, x_true, sigma, b = toy
+    _say("case: autograd forward with out-of-range widths")
+    A = dev(x_true)
+    s_bad = sigma.copy()
+    s_bad[5] = 1.5 * w.smax
+    s_bad[9] = -1.0
+    y_ok = host(gpair_forward(A, dev(sigma), plan))
+    assert np.isfinite(y_ok).all()
+    with pytest.raises(ValueError, match="2 kernel"):
+        gpair_forward(A, dev(s_bad), plan)
+    y_clamped = host(gpair_forward(A, dev(s_bad), plan, check=False))
+    s_clamp = sigma.copy()
+    s_clamp[5] = w.smax
+    s_clamp[9] = w.smax
+    y_ref = host(gpair_forward(A, dev(s_clamp), plan))
+    assert rel_l2(y_clamped, y_ref) <= 1e-6
