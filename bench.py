@@ -56,7 +56,7 @@ MEASURED_TRAFFIC = {
 
 # The same for the anisotropic kernels (aniso.hip).
 MEASURED_TRAFFIC_ANISO = {
-    "b0b6ea796235c811": {"aniso_forward_kernel": 2.263e+09, "aniso_adjoint_kernel": 8.786e+08},
+    "cd32d60d0335da76": {"aniso_forward_kernel": 2.263e+09, "aniso_adjoint_kernel": 8.776e+08},
 }
 
 # The same for the ASSA kernels (assa.hip).

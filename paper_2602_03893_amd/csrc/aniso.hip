@@ -59,6 +59,10 @@ static_assert(offsetof(AnisoRec, fcz) == offsetof(KernelRec, fcz) &&
 
 constexpr int kAnisoWaves = 4;   // forward waves per workgroup
 constexpr int kTapRunAniso = 16; // taps between exact Gaussian factors
+// Floats of LDS past the adjoint's stage: the unrolled gather (at most 18
+// taps) reads its whole unrolled length from a window that starts inside its
+// row, and masks what lies past the lane's own window.
+constexpr int kAnisoStagePad = 32;
 // Largest condition number lambda_max/lambda_min of a covariance whose pairs
 // go through the float32 filter: sigma_n^2 from the float32 quadratic form is
 // then within about 24 kappa float32 units (6e-6 relative at 2.5), which keeps
@@ -335,6 +339,17 @@ __global__ __launch_bounds__(256) void aniso_det_finish_kernel(const long long *
     y[i] = (float)((double)y64[i] * G);
 }
 
+// The largest n over the wave's active lanes when it is below 32 (31
+// otherwise), by five ballots: no cross-lane data movement, and the result is
+// wave-uniform.
+__device__ __forceinline__ int wave_max_small(int n) {
+  int m = 0;
+#pragma unroll
+  for (int b = 16; b > 0; b >>= 1)
+    if (__ballot(n >= m + b) != 0) m += b;
+  return m;
+}
+
 __device__ __forceinline__ void lds_add_fx(int *p, float v) {
   int n;
   asm volatile("v_cvt_rpi_i32_f32 %0, %1" : "=v"(n) : "v"(v));
@@ -355,6 +370,35 @@ __device__ __forceinline__ void aniso_taps(int *pa, float f, float q, float d, f
       tv = fmaf(q, tv, -f);
       q *= rq;
     }
+  }
+}
+
+// The taps of one pair from a staged residual row (rp at the pair's first
+// sample), unrolled for NT samples of which the lane's own n are read:
+// s1 += delta e u, with S3 s3 += delta e u^3, with CEN s0 += delta e and
+// s2 += delta e u^2 (u in samples, e by the ratio recurrence).
+template <int NT, bool S3, bool CEN>
+__device__ __forceinline__ void aniso_gather(const float *rp, float f, float q, float d, float rq,
+                                             int n, float &s0, float &s1, float &s2, float &s3) {
+  float dl[NT];
+  // Every read stays in the stage: the window starts inside its row and the
+  // stage carries kAnisoStagePad floats past its last row.
+#pragma unroll
+  for (int i = 0; i < NT; ++i) dl[i] = rp[i];
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    if (i >= n) dl[i] = 0.0f;
+    const float t = dl[i] * f;
+    const float pd = t * d;
+    s1 += pd;
+    if (S3) s3 = fmaf(pd, d * d, s3);
+    if (CEN) {
+      s0 += t;
+      s2 = fmaf(pd, d, s2);
+    }
+    d -= 1.0f;
+    f *= q;
+    q *= rq;
   }
 }
 
@@ -419,9 +463,7 @@ __global__ __launch_bounds__(WAVES * kWave) void aniso_forward_kernel(
       const float w = r.A * r.sq * (p.isn * p.isn * p.isn) * wsc * p.rinv;
       int *const pa = col + p.o * kWave;
       const int n = p.ntap;
-      int nmax = n;
-      for (int off = 32; off > 0; off >>= 1) nmax = max(nmax, __shfl_xor(nmax, off, kWave));
-      nmax = __builtin_amdgcn_readfirstlane(nmax);
+      const int nmax = wave_max_small(n);
       if (nmax <= 18) {
         const float f0 = w * __builtin_amdgcn_exp2f(gs.c * p.d0 * p.d0);
         const float q0 = __builtin_amdgcn_exp2f(fmaf(gs.k1, p.d0, gs.c));
@@ -438,14 +480,15 @@ __global__ __launch_bounds__(WAVES * kWave) void aniso_forward_kernel(
         }
         continue;
       }
-      for (int i0 = 0; i0 < nmax; i0 += kTapRunAniso) {
+      // Longer windows: each lane runs its own count.
+      for (int i0 = 0; i0 < n; i0 += kTapRunAniso) {
         const float d = p.d0 - (float)i0;
         float f = w * __builtin_amdgcn_exp2f(gs.c * d * d);
         float q = __builtin_amdgcn_exp2f(fmaf(gs.k1, d, gs.c));
         float tv = f * d;  // t_i = f_i u_i; t_{i+1} = q_i t_i - f_{i+1}
-        const int iend = min(i0 + kTapRunAniso, nmax);
+        const int iend = min(i0 + kTapRunAniso, n);
         for (int i = i0; i < iend; ++i) {
-          if (i < n) lds_add_fx(pa + i * kWave, tv);
+          lds_add_fx(pa + i * kWave, tv);
           f *= q;
           tv = fmaf(q, tv, -f);
           q *= gs.rq;
@@ -592,7 +635,28 @@ __global__ __launch_bounds__(BLOCK) void aniso_adjoint_kernel(const double4 *__r
       // In samples: s0 = sum delta e, s1 = sum delta u e, s2 = sum delta u^2 e,
       // s3 = sum delta u^3 e.
       float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
-      for (int i0 = 0; i0 < p.ntap; i0 += kTapRunAniso) {
+      const int nmax = wave_max_small(p.ntap);
+      if (nmax <= 18) {
+        // Unrolled for the wave's longest window, each lane masked to its own.
+        const float f0 = __builtin_amdgcn_exp2f(gs.c * p.d0 * p.d0);
+        const float q0 = __builtin_amdgcn_exp2f(fmaf(gs.k1, p.d0, gs.c));
+        switch (nmax) {
+#define GPAIR_ANISO_GATHER(k)                                                          \
+  case k:                                                                              \
+    aniso_gather<k, SIGMA || CENTRES, CENTRES>(rp, f0, q0, p.d0, gs.rq, p.ntap, s0, s1, \
+                                               s2, s3);                                \
+    break;
+          GPAIR_ANISO_GATHER(1) GPAIR_ANISO_GATHER(2) GPAIR_ANISO_GATHER(3)
+          GPAIR_ANISO_GATHER(4) GPAIR_ANISO_GATHER(5) GPAIR_ANISO_GATHER(6)
+          GPAIR_ANISO_GATHER(7) GPAIR_ANISO_GATHER(8) GPAIR_ANISO_GATHER(9)
+          GPAIR_ANISO_GATHER(10) GPAIR_ANISO_GATHER(11) GPAIR_ANISO_GATHER(12)
+          GPAIR_ANISO_GATHER(13) GPAIR_ANISO_GATHER(14) GPAIR_ANISO_GATHER(15)
+          GPAIR_ANISO_GATHER(16) GPAIR_ANISO_GATHER(17) GPAIR_ANISO_GATHER(18)
+#undef GPAIR_ANISO_GATHER
+          default: break;
+        }
+      }
+      for (int i0 = nmax <= 18 ? p.ntap : 0; i0 < p.ntap; i0 += kTapRunAniso) {
         float d = p.d0 - (float)i0;
         float f = __builtin_amdgcn_exp2f(gs.c * d * d);
         float q = __builtin_amdgcn_exp2f(fmaf(gs.k1, d, gs.c));
@@ -756,7 +820,7 @@ hipError_t launch_aniso_adjoint(const gpair_plan_s *p, const float *delta, float
   a.nsig = p->nsig;
   const double smax = p->sigma_max * (1.0 + 1e-6);
   a.smax2 = smax * smax;
-  const size_t lds = (size_t)p->La * kAdjSensorsPerStage * sizeof(float);
+  const size_t lds = ((size_t)p->La * kAdjSensorsPerStage + kAnisoStagePad) * sizeof(float);
   const unsigned int grid = xcd_grid_a(a.nlogical);
   const double4 *sens = (const double4 *)ws_sens(p);
 #define GPAIR_ANISO_ADJ(B)                                                                 \
