@@ -42,15 +42,12 @@ FLOP_PAIR_CENTRES = 16  # its per-pair combination along (c - s)/r
 # wave64 VALU instructions issued per CU per clock (2.4 GHz) by each operator
 # kernel: rocprofv3 SQ_INSTS_VALU / (duration x 256 CUs x 2.4 GHz), keyed like
 # MEASURED_TRAFFIC.
-# (b9485a0e7eba45ec: operators.hip + filter.h after the filter's block
-# constants moved to filter.h; the built code is the same instruction for
-# instruction as the profiled edc5b40f6b50557d, operators.hip alone.)
 MEASURED_VALU = {
-    "b9485a0e7eba45ec": {"forward_kernel": 1.356, "adjoint_kernel": 1.434},
+    "017f0377afb88363": {"forward_kernel": 1.350, "adjoint_kernel": 1.431},
 }
 
 MEASURED_TRAFFIC = {
-    "b9485a0e7eba45ec": {"forward_kernel": 2.295e9, "adjoint_kernel": 0.6965e9},
+    "017f0377afb88363": {"forward_kernel": 2.330e9, "adjoint_kernel": 0.7538e9},
 }
 
 

@@ -564,6 +564,10 @@ constexpr int kAdjRankMinSensors = 256;
 // What the adjoint accumulates: MODE 0 the amplitude gradient; 1 also the
 // sigma-gradient; 2 also the centre gradient.
 constexpr int kAdjA = 0, kAdjSigma = 1, kAdjCentres = 2;
+// Tap counts for which the A and sigma modes sum moments about the window's
+// middle tap (shorter windows cancel in float32; longer ones keep the direct
+// sums for their registers).
+constexpr int kAdjMomentTaps[2] = {7, 12};
 
 // Gather the taps of one kernel-sensor pair from a staged residual row (row
 // points at the pair's first sample): NT samples, of which the first
@@ -588,6 +592,35 @@ __device__ __forceinline__ void gather_taps(const float *row, float f, float q, 
       const bool inside = i < ntap - 1 || (i == ntap - 1 && last_ok);
       if (!inside) dl[i] = 0.0f;
     }
+  }
+  if (MODE != kAdjCentres && NT >= kAdjMomentTaps[0] && NT <= kAdjMomentTaps[1]) {
+    // t_i = f_i u_i by the forward's recurrence t_{i+1} = q_i t_i - f_{i+1};
+    // with C the middle tap and u_i = uc - (i - C), uc = d - C:
+    //   sum w u^2 = uc (uc M0 + M1) + M2,
+    // w = delta t, M0 = sum w, M1 = -2 sum w (i - C), M2 = sum w (i - C)^2.
+    constexpr int C = (NT - 1) / 2;
+    float t = f * d;
+    float m0 = 0.0f, m1 = 0.0f, m2 = 0.0f;
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      const float w = dl[i] * t;
+      m0 += w;
+      if (MODE >= kAdjSigma && i != C) {
+        m1 = fmaf(w, (float)(-2 * (i - C)), m1);
+        m2 = fmaf(w, (float)((i - C) * (i - C)), m2);
+      }
+      if (i + 1 < NT) {
+        f *= q;
+        t = fmaf(q, t, -f);
+        q *= rq;
+      }
+    }
+    s1 += m0;
+    if (MODE >= kAdjSigma) {
+      const float uc = d - (float)C;
+      s3 += fmaf(uc, fmaf(uc, m0, m1), m2);
+    }
+    return;
   }
 #pragma unroll
   for (int i = 0; i < NT; ++i) {
@@ -789,8 +822,12 @@ __device__ __forceinline__ void adjoint_body(const double4 *__restrict__ sens, c
       const double R = sqrt(fma(dz, dz, fma(dy, dy, dx * dx)));
       const int nb = (int)floor((R - T.rho) * a.inv_vdt - a.t0_over_dt - a.hmax) - 1;
       nbs[t] = nb;
+      // The reference point's conversions are redone here every stage rather
+      // than held in registers through the pair loops.
+      TileInfo Tr = T;
+      asm volatile("" : "+s"(Tr.cx), "+s"(Tr.cy), "+s"(Tr.cz));
       BlockLane bl;
-      block_lane(s, T, nb, a.inv_vdt, a.t0_over_dt, bl);
+      block_lane(s, Tr, nb, a.inv_vdt, a.t0_over_dt, bl);
       su[t] = make_float4(bl.m2ux, bl.m2uy, bl.m2uz, bl.inv2R);
       sv[t] = make_float4(bl.Rf, bl.Xf, __int_as_float(bl.Xi), 0.0f);
     }
@@ -836,7 +873,9 @@ __device__ __forceinline__ void adjoint_body(const double4 *__restrict__ sens, c
     // The sums ran over e/r with offsets in samples: gA = Delta/2 sum delta u e/r,
     // gsigma = A/2 (Delta/sigma)^3 sum delta u^3 e/r, Delta/sigma = n_sigma/h.
     // gc = A/2 sum over pairs of (c - s)/r G.
-    const int32_t k = a.perm[i];
+    // The kernel's index again from the ranking in LDS (nothing holds it
+    // through the stages).
+    const int32_t k = a.perm[T.start + order[t]];
     a.gA[k] = (float)(accA * 0.5 * a.vdt);
     if (MODE >= kAdjSigma && a.gS) {
       const double ds = a.nsig / r.h;
