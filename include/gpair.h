@@ -108,7 +108,7 @@ typedef struct gpair_geometry {
   int32_t fwd_tile;
   int32_t adj_tile;
   int32_t fwd_waves;
-  int32_t deterministic;  /* != 0: bitwise reproducible forward (see gpair_forward) */
+  int32_t deterministic;  /* != 0: bitwise reproducible forward (gpair_forward, gpair_forward_aniso) */
 } gpair_geometry;
 
 typedef struct gpair_plan_s *gpair_plan;
