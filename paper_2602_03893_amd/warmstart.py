@@ -184,7 +184,9 @@ def train(problem, X, T, Xte, Tte, epochs, batch=4, lr=1e-3, seed=0, log=print,
 # under 5 %.  At lr_A 0.16: beta2 0.99 / 0.98 / 0.95 / 0.9 took 289 / 222 /
 # 175 / 120 iterations, 0.8 and 0.5 did not converge in 1000; beta1 0.8 or
 # 0.95 and warm-restart schedules were slower.  At beta2 0.9, lr_A 0.08 took
-# 110-112 iterations on all four seeds from either start (0.32 failed).
+# 110-112 iterations on all four seeds from either start (0.32 failed; 0.05
+# and 0.12 took 109-117; beta1 0.85 and 0.8 slowed the zero start to
+# 104-149 and 189-242).
 EVAL_LR_A, EVAL_LR_SIGMA_REL, EVAL_BETA2 = 0.08, 1e-3, 0.9
 
 
