@@ -261,3 +261,29 @@ def test_deterministic_anisotropic_forward():
     e = rel_l2(y1, y_ref)
     _say(f"  deterministic forward {e:.3e}")
     assert e <= TOL
+
+
+def test_autograd_rejects_covariances_the_operator_would_replace():
+    """A covariance outside the admitted set (not positive definite, or an
+    eigenvalue above sigma_max^2) makes the autograd forward raise; with
+    check=False the output equals the forward at sigma_max^2 I for those
+    kernels."""
+    from paper_2602_03893_amd import aniso_forward
+    _say("case: toy workload, autograd with inadmissible covariances")
+    w = I.WORKLOADS["toy"]
+    cen, sen = I.geometry_arrays(w)
+    plan, g = plan_of(cen, sen, w.n_samples, w.smax)
+    A = dev(I.phantom(w))
+    S6 = I.covariances(w.n_kernels, seed=231, lo=0.4 * w.smax, hi=0.8 * w.smax)
+    y_ok = host(aniso_forward(A, dev(S6), plan))
+    assert np.isfinite(y_ok).all()
+    bad = S6.copy()
+    bad[:, 7] = [2.0 * w.smax ** 2, 0.5 * w.smax ** 2, 0.5 * w.smax ** 2, 0.0, 0.0, 0.0]
+    bad[:, 11] = [0.5 * w.smax ** 2, 0.5 * w.smax ** 2, -0.1 * w.smax ** 2, 0.0, 0.0, 0.0]
+    with pytest.raises(ValueError, match="2 kernel"):
+        aniso_forward(A, dev(bad), plan)
+    y_rep = host(aniso_forward(A, dev(bad), plan, check=False))
+    fixed = bad.copy()
+    fixed[:, 7] = fixed[:, 11] = [w.smax ** 2, w.smax ** 2, w.smax ** 2, 0.0, 0.0, 0.0]
+    y_ref = host(aniso_forward(A, dev(fixed), plan))
+    assert rel_l2(y_rep, y_ref) <= 1e-6
