@@ -982,6 +982,9 @@ def main():
                      "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": MEASURED_TRAFFIC.get(kernel_source_hash(), {}).get(dom),
                      "frac_fp64_at_fp64_peak": frac64,
+                     "frac_by_kernel": {
+                         "forward_kernel": flop_fwd / (t_fwd * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
+                         "adjoint_kernel": flop_adj / (t_adj * 1e-3) / 1e12 / PEAK_FP32_TFLOPS},
                      "exp_per_s": exp_rate,
                      "exp_frac_of_measured": exp_rate / (peaks["v_exp_f32"]["wave_instr_per_s"] * 64),
                      "valu_per_cu_per_clk": MEASURED_VALU.get(kernel_source_hash(), {}).get(dom),
